@@ -1,0 +1,192 @@
+"""Throughput of the radiation step on one MI355X.
+
+Workload (the throughput configuration): a periodic jittered-lattice Voronoi
+mesh of 128^3 = 2,097,152 cells, 80 discrete ordinates, first-order upwind
+transport plus the implicit source, 50 steps; inputs seeded and synthetic,
+resident in HBM before timing starts.  Both precision forms run on the same
+GPU from the same initial state: FP32 intensities/transport with the FP64
+source solve and bookkeeping (the headline `value`) and all-FP64.
+
+Prints ONE JSON line.  `value` = cell-angle updates per second of the FP32
+form (N cells * K angles * steps / wall time of the timed steps).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_INDEX = 3  # 128^3 cells x 80 angles x 50 steps
+
+
+def algorithmic_bytes(N, F, K, dtype):
+    """Bytes one fused first-order step must move at minimum: each intensity read and written
+    once (N K s_I), each face's cell pair and (A n, A w.n) once, the half-face index (row pointers
+    and one signed id per half-face), and 120 B of FP64 cell state (V, D, rho, mom r/w, E_g r/w,
+    kP, kJ, ks, V')."""
+    sI = 4 if dtype == "f32" else 8
+    sg = 4 if dtype == "f32" else 8
+    return N * K * 2 * sI + F * (8 + 4 * sg) + (N + 1) * 4 + 2 * F * 4 + 120 * N
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2002_08377_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("source_hash") != kernel_source_hash():
+        return None
+    ent = data.get("kernels", {}).get(kernel_key)
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def run_form(prob, mesh, angles, dtype_code, steps, warmup, log):
+    import torch
+    from paper_2002_08377_amd import rt
+    st = prob.state
+    ph = prob.phys
+    params = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, prob.dt, dtype_code, rt.UPWIND1)
+    td = rt.torch_dtype(dtype_code)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    I = d(st.I).to(td).contiguous()
+    I2 = torch.empty_like(I)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    rho, kP, kJ, ks = d(st.rho), d(st.kP), d(st.kJ), d(st.ks)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        rt.step(mesh, params, angles, I, I2, vol, rho, mom, etot, kP, kJ, ks, stream=stream)
+        I, I2 = I2, I
+    # restart from the initial state so both forms advance the same trajectory
+    I.copy_(d(st.I).to(td))
+    vol.copy_(d(st.vol)); mom.copy_(d(st.mom)); etot.copy_(d(st.etot))
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        rt.step(mesh, params, angles, I, I2, vol, rho, mom, etot, kP, kJ, ks, stream=stream)
+        ev[i][1].record(stream)
+        I, I2 = I2, I
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    diag = rt.diagnostics(mesh, params, angles, I, vol, etot, mom)
+    log(f"  dtype={'f32' if dtype_code == rt.F32 else 'f64'}: {wall * 1e3 / steps:.3f} ms/step wall, "
+        f"kernel mean {np.mean(kern_ms):.3f} ms, min I {diag[8]:.3e}")
+    return dict(wall=wall, kernel_ms=float(np.mean(kern_ms)), I=I.double().cpu().numpy(), diag=diag,
+                etot=etot.cpu().numpy())
+
+
+def cpu_baseline(prob, steps, log):
+    """The FP64 oracle (plain C, OpenMP) on the host cores: `steps` full steps of the same workload."""
+    import oracle as orc
+    st = prob.state
+    om = orc.OracleMesh(prob.mesh, st.mesh_vel)
+    s0 = orc.OState(st.I, st.vol, st.mom, st.etot)
+    t0 = time.perf_counter()
+    orc.run(om, prob.dirs, prob.weights, prob.phys, prob.dt, s0, st.rho, st.kP, st.kJ, st.ks, steps)
+    dt = time.perf_counter() - t0
+    N, K = st.I.shape
+    log(f"  oracle: {steps} steps in {dt:.2f} s on {orc.num_threads()} threads")
+    return dict(value=N * K * steps / dt, unit="cell-angle updates/s", cores=orc.num_threads(), kind="oracle",
+                sample=f"{steps} full FP64 first-order steps of the {N}-cell x {K}-angle workload "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=None, help="override cells per side (default 128)")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this library has no multi-GPU path (asked for {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2002_08377_amd import inputs as inp
+    from paper_2002_08377_amd import rt
+
+    rt.lib()
+    t0 = time.perf_counter()
+    prob = inp.make_problem(WORKLOAD_INDEX, n=args.n)
+    N, K, F = prob.mesh.n_cells, prob.dirs.shape[0], prob.mesh.n_faces
+    log(f"workload: {N} cells, {F} faces, {K} angles; inputs built in {time.perf_counter() - t0:.1f} s")
+    mesh = rt.Mesh.from_inputs(prob.mesh, prob.state.mesh_vel, k_max=K)
+    angles = rt.AngleSet(prob.dirs, prob.weights)
+
+    res = {}
+    for name, code in (("f32", rt.F32), ("f64", rt.F64)):
+        res[name] = run_form(prob, mesh, angles, code, args.steps, args.warmup, log)
+
+    ca = N * K * args.steps
+    err = float(np.max(np.abs(res["f32"]["I"] - res["f64"]["I"])) / np.max(np.abs(res["f64"]["I"])))
+
+    def roof(name):
+        b = algorithmic_bytes(N, F, K, name)
+        ach = b / (res[name]["kernel_ms"] * 1e-3) / 1e9
+        tr = measured_traffic(f"step_upwind1_{name}")
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
+                "kernel": "k_step (fused upwind transport + implicit source)",
+                "algorithmic_bytes_per_launch": int(b), "kernel_ms": round(res[name]["kernel_ms"], 4)}
+
+    out = {
+        "metric": "cell-angle updates/s per RT step (fwd)",
+        "value": ca / res["f32"]["wall"],
+        "unit": "cell-angle updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["f32"]["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"throughput_{round(N ** (1 / 3))}c_{K}a", "cells": N, "faces": F, "angles": K,
+                   "steps": args.steps, "scheme": "upwind1",
+                   "precision": "FP32 intensities and transport, FP64 source solve and bookkeeping",
+                   "mesh": "periodic Voronoi of a +-0.2 jittered cubic lattice, Morton-ordered cells"},
+        "roofline": roof("f32"),
+        "fp64": {"value": ca / res["f64"]["wall"], "ms_per_step": res["f64"]["wall"] * 1e3 / args.steps,
+                 "dtype": "f64", "roofline": roof("f64")},
+        "f32_over_f64": res["f64"]["wall"] / res["f32"]["wall"],
+        "f32_vs_f64_rel_err_I": err,
+    }
+    mesh.free()
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

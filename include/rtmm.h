@@ -1,0 +1,226 @@
+/*
+ * rtmm.h -- C ABI of the MI355X radiation-step library (librtmm.so).
+ *
+ * The library advances the specific intensities of discrete-ordinates
+ * radiative transfer in the reduced-speed-of-light approximation on a periodic
+ * Voronoi mesh, as in Chang, Davis & Jiang, "Time Dependent Radiation
+ * Hydrodynamics on a Moving Mesh": transport written as a finite-volume
+ * conservation law with per-face, per-angle upwind fluxes in the frame of the
+ * moving face (section 2.2), followed by the per-cell implicit source update
+ * that couples every angle to the gas energy and momentum (section 2.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: RT_OK (0) or a negative RT_E* code.  rt_strerror() names a
+ *    code; rt_last_error() returns the message of the calling thread's last
+ *    failing call.  Nothing throws or exits across this ABI.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *    Step calls only enqueue work on it: they never synchronise and never
+ *    allocate; scratch is sized when the mesh is uploaded.  rt_mesh_upload,
+ *    rt_mesh_free and rt_diagnostics synchronise `stream`.
+ *  - Memory: "device" pointers are HIP device memory owned by the caller,
+ *    contiguous, at least 8-byte aligned; "host" pointers are host memory read
+ *    during the call only.  The library owns the rt_mesh and everything in it.
+ *  - Layouts: per-cell vectors are [N][3] row-major; intensities are [N][K]
+ *    row-major (angle fastest); limited gradients are [N][3][K].
+ *  - Precision: with dtype RT_F64 intensity arrays are double; with RT_F32 they
+ *    are float and transport runs in float, while the gas state, the opacities,
+ *    the moment sums, the temperature root and the energy/momentum bookkeeping
+ *    stay double.
+ *  - Units: intensities are carried in energy-density units (equilibrium value
+ *    a T^4 / 4 pi), so E_r = 4 pi sum_k W_k I_k and F_r = 4 pi c sum_k W_k n_k I_k.
+ *    The gas temperature is T = (E_g - |rho v|^2 / 2 rho) / (rho cv).
+ *  - Concurrency: calls on one mesh must not overlap in time on different
+ *    streams (they share the mesh's scratch buffers).
+ */
+#ifndef RTMM_H
+#define RTMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTMM_VERSION 1
+
+enum {
+  RT_OK = 0,
+  RT_EINVAL = -1,     /* invalid argument (null pointer, bad size, bad value) */
+  RT_ENOMEM = -2,     /* device allocation failed (upload only) */
+  RT_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+  RT_ENONFINITE = -4, /* non-finite values found (diagnostics) */
+  RT_ESTATE = -5      /* the mesh was not prepared for this call (missing upload flag) */
+};
+
+enum { RT_F64 = 0, RT_F32 = 1 };              /* rt_params.dtype */
+enum { RT_UPWIND1 = 0, RT_PLM_VL2 = 1 };      /* rt_params.scheme */
+
+/* rt_mesh_upload flags: which scratch to allocate. */
+enum {
+  RT_MESH_PLM = 1,     /* half-step intensities and limited gradients for RT_PLM_VL2 */
+  RT_MESH_ADJOINT = 2  /* one [N][K_max] adjoint buffer for rt_step_adjoint */
+};
+
+#define RT_K_MAX 128
+#define RT_NDIAG 10
+
+typedef struct rt_mesh rt_mesh;
+
+/* Physical and numerical parameters of one call. */
+typedef struct {
+  double c_red;   /* reduced speed of light cbar (transport speed, section 2.1), > 0 */
+  double c_light; /* speed of light c (Lorentz factors, gas coupling), >= c_red */
+  double a_rad;   /* radiation constant a, >= 0 */
+  double cv;      /* specific heat: rho cv = rho k_B / (mu (gamma - 1) m_p) of eq. 26, > 0 */
+  double dt;      /* time step, > 0 */
+  int32_t dtype;  /* RT_F64 or RT_F32 */
+  int32_t scheme; /* RT_UPWIND1 or RT_PLM_VL2 */
+} rt_params;
+
+/* Discrete ordinates: K unit directions and weights summing to one (device memory). */
+typedef struct {
+  int32_t K;            /* 1 <= K <= k_max of the mesh (and <= RT_K_MAX) */
+  const double *dir;    /* device [K][3], unit vectors */
+  const double *weight; /* device [K], sum = 1 */
+} rt_angles;
+
+const char *rt_strerror(int code);
+const char *rt_last_error(void);
+int rt_version(void);
+
+/*
+ * Upload a periodic Voronoi mesh and prepare it for steps (section 2: cells,
+ * faces, and the face velocity of eq. 9).  All arrays are HOST memory:
+ *   gen_pos[N][3]   generator positions r_i
+ *   com[N][3]       cell centres of mass s_i (reconstruction origin)
+ *   vol[N]          cell volumes of the tessellation (> 0)
+ *   mesh_vel[N][3]  generator velocities w_i, held fixed over the run
+ *   face_cells[F][2] cell pair (i, j) of each face, i != j
+ *   face_shift[F][3] image of j adjacent to i is gen_pos[j] + shift * box
+ *   face_area[F]    (> 0), face_normal[F][3] unit, from i towards j,
+ *   face_centroid[F][3] in the frame of i
+ *   box             periodic box side
+ * The library computes on the device each face's normal speed w~.n (eq. 9),
+ * the half-face table grouped by cell (a compressed-row index, so every cell
+ * gathers its fluxes without atomics) and the rate of change of each cell
+ * volume D_i = sum_faces A (w~.n) (outward positive; the volume update is
+ * V^{n+1} = V^n + dt D_i).  k_max bounds K in later calls; flags (RT_MESH_*)
+ * select scratch.  Errors: RT_EINVAL (sizes, indices out of range, area <= 0,
+ * non-unit normal, a cell whose faces do not close: |sum A n| > 1e-8 V^(2/3)),
+ * RT_ENOMEM, RT_EHIP.  On error *out is NULL.  Synchronises `stream`.
+ */
+int rt_mesh_upload(rt_mesh **out, int64_t n_cells, int64_t n_faces, int32_t k_max, int32_t flags,
+                   const double *gen_pos, const double *com, const double *vol, const double *mesh_vel,
+                   const int32_t *face_cells, const int8_t *face_shift, const double *face_area,
+                   const double *face_normal, const double *face_centroid, double box, void *stream);
+
+/* Release the mesh and its device memory (NULL is accepted).  Synchronises the device. */
+int rt_mesh_free(rt_mesh *mesh);
+
+/* Sizes of an uploaded mesh (any output pointer may be NULL). */
+int rt_mesh_info(const rt_mesh *mesh, int64_t *n_cells, int64_t *n_faces, int64_t *n_half_faces,
+                 int32_t *k_max, int32_t *flags);
+
+/* Copy the face normal speeds w~.n [F] (eq. 9) and the volume rates D [N] into
+ * device arrays (either may be NULL).  Asynchronous on `stream`. */
+int rt_mesh_geometry(const rt_mesh *mesh, double *face_speed, double *vol_rate, void *stream);
+
+/*
+ * Transport alone over params->dt (section 2.2), on `stream`:
+ *  RT_UPWIND1: per face and angle the face-frame speed s = cbar n_k.n_f - w~.n_f
+ *    picks the upwind cell; the charge dt A s I_up leaves the cell the normal
+ *    points out of (eq. 8); I_out = (V I_in - sum of charges) / V_new.
+ *  RT_PLM_VL2: the van Leer two-stage form (section 2, steps 2b-5) without the
+ *    source: a first-order half step gives I_half, whose limited linear
+ *    reconstruction (rt_gradient) gives the face states of the full step.
+ * I_in [N][K] (device, dtype) and I_out must not overlap.  vol [N] (device) holds
+ * V^n on entry and V^{n+1} = V^n + dt D on return.  RT_ESTATE if RT_PLM_VL2 is
+ * asked of a mesh uploaded without RT_MESH_PLM.
+ */
+int rt_transport_step(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_in,
+                      void *I_out, double *vol, void *stream);
+
+/*
+ * Implicit source update over params->dt (section 2.3, the four-step
+ * algorithm), in place on I [N][K]:
+ *  1. lab moments E^n, F^n;  2. boost each angle to the comoving frame
+ *  (Gamma_k = gamma (1 - v.n_k/c), I~ = Gamma^4 I, W~ = N W / Gamma^2), solve the
+ *  temperature equation with J~ eliminated for T^{n+1};  3. implicit update of
+ *  every I~_k and boost back;  4. E_g += (c/cbar)(E^n - E^{n+1}),
+ *  rho v += (F^n - F^{n+1}) / (c cbar).
+ * rho, kP, kJ, ks [N] (device) are read; mom [N][3] and etot [N] are updated in
+ * place; T_new [N] (device, nullable) receives T^{n+1}.  J~ is eliminated in
+ * the corrected form J~ = (S_I + y kP S_G a T^4/4pi)/(1 - y ks S_G), y = dt cbar rho
+ * (the printed eq. 29 drops rho and misplaces kJ), with 1 - y ks S_G evaluated
+ * as S_1 + y kJ S_G, S_1 = sum W~/(1 + y (kJ+ks) Gamma), which has no
+ * cancellation.  The quartic A T^4 + B T - C = 0 is solved by Newton's method
+ * from above in FP64.
+ */
+int rt_source_implicit(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, void *I,
+                       const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
+                       const double *ks, double *T_new, void *stream);
+
+/*
+ * One radiation step: transport then source.  RT_UPWIND1: one fused pass (each
+ * intensity row read once and written once).  RT_PLM_VL2: stage 1 = first-order
+ * transport and source over dt/2 (its gas changes are discarded), stage 2 =
+ * reconstructed fluxes of the half-step state applied to the start-of-step
+ * charges over dt, then the source over dt on the start-of-step gas.
+ * Arguments as rt_transport_step and rt_source_implicit; I_in and I_out must not
+ * overlap.
+ */
+int rt_step(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_in, void *I_out,
+            double *vol, const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
+            const double *ks, double *T_new, void *stream);
+
+/*
+ * Limited linear reconstruction of every angle (section 2.2 item ii): the
+ * Voronoi gradient estimator of S10 with the geometric cell volumes, limited by
+ * the Barth-Jespersen factor so that extrapolations from the centre of mass to
+ * every face centroid stay within the range of the cell and its neighbours.
+ * I [N][K] (device, dtype) in, grad [N][3][K] (device, dtype) out.  Needs
+ * RT_MESH_PLM only for the scheme, not for this call.
+ */
+int rt_gradient(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I, void *grad,
+                void *stream);
+
+/*
+ * Reverse (adjoint) of one RT_UPWIND1 rt_step for the gradient of a scalar loss.
+ * Inputs of the forward step: I_star = intensities after transport (the source
+ * input), vol_n = V^n, rho, mom_n, etot_n (gas before the source), kP, kJ, ks.
+ * Adjoints: lamI [N][K] (dtype) holds dL/dI^{n+1} on entry and dL/dI^n on
+ * return; lamE [N] and lamM [N][3] hold dL/d(etot, mom)^{n+1} on entry and
+ * dL/d(etot, mom)^n on return; dL_dkP, dL_dkJ [N] are incremented (nullable).
+ * The temperature root enters through the implicit function theorem.  Needs a
+ * mesh uploaded with RT_MESH_ADJOINT (RT_ESTATE otherwise).
+ */
+int rt_step_adjoint(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_star,
+                    const double *vol_n, const double *rho, const double *mom_n, const double *etot_n,
+                    const double *kP, const double *kJ, const double *ks, void *lamI, double *lamE, double *lamM,
+                    double *dL_dkP, double *dL_dkJ, void *stream);
+
+/*
+ * Emergent-flux loss L = sum_f u_f A_f 4 pi c sum_k W_k (n_k.n_f) I_up(f,k),
+ * the radiative flux through each weighted face with the upwind intensity of
+ * each angle (chosen by the sign of n_k.n_f).  face_weight [F] (device, signed:
+ * the sign orients the face, zero for faces outside the loss).  *loss (device
+ * double) is overwritten; when seed != NULL, dL/dI is ADDED to seed [N][K]
+ * (dtype).  Deterministic: no atomics.
+ */
+int rt_flux_loss(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I,
+                 const double *face_weight, double *loss, void *seed, void *stream);
+
+/*
+ * Conservation diagnostics into out[RT_NDIAG] (HOST): sum V E_g,
+ * sum V (c/cbar) E_r, sum V rho v (3), sum V F_r/(c cbar) (3), min I, and the
+ * number of non-finite entries of I, etot and mom.  Synchronises `stream`.
+ * Returns RT_ENONFINITE (with out filled) when that count is non-zero.
+ */
+int rt_diagnostics(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I,
+                   const double *vol, const double *etot, const double *mom, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTMM_H */

@@ -78,6 +78,8 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = None
+        lib.or_num_threads.argtypes = []
+        lib.or_num_threads.restype = INT
         lib.or_quartic_root.argtypes = [D, D, D]
         lib.or_quartic_root.restype = D
         for name in ("or_flux_loss", "or_flux_loss_cs"):
@@ -217,6 +219,11 @@ def flux_loss(om: OracleMesh, dirs, W, c_light, I, face_weight, want_seed=False,
     _load().or_flux_loss(om.ref, K, _p(_f64(dirs)), _p(_f64(W)), c_light, _p(I), _p(fw), _p(seed), _p(out))
     L = float(out[0])
     return (L, seed) if want_seed else L
+
+
+def num_threads() -> int:
+    """Threads used by the oracle's OpenMP loops."""
+    return int(_load().or_num_threads())
 
 
 def quartic_root(A, B, C):

@@ -311,6 +311,18 @@ static REAL quartic_root(REAL A, REAL B, REAL C) {
 }
 
 #ifndef OR_COMPLEX
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Number of threads the oracle's parallel loops use. */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* The temperature root alone, exported for the tests. */
 double or_quartic_root(double A, double B, double C) { return quartic_root(A, B, C); }
 #endif

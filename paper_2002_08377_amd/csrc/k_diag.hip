@@ -1,0 +1,227 @@
+// Grid reductions: conservation diagnostics (section 2.3.1) and the emergent-flux
+// loss with its seed.  Each cell group reduces over its angles, each workgroup
+// over its cells through LDS, and one final workgroup over the per-workgroup
+// partials in a fixed order, so results are deterministic (no atomics).
+#include "rt_device.h"
+
+namespace {
+
+constexpr int ND = RT_NDIAG;
+
+// Block reduction of NV values held by lane 0 of each cell group; kinds: 0 sum, 1 min.
+template <int NV, int LPC>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], const int (&kind)[NV], double *out_blk) {
+  __shared__ double sh[RT_BLOCK / LPC][NV];
+  constexpr int CPB = RT_BLOCK / LPC;
+  const int g = threadIdx.x / LPC, l = threadIdx.x % LPC;
+  if (l == 0)
+    for (int i = 0; i < NV; ++i) sh[g][i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    double acc = sh[0][i];
+    for (int c = 1; c < CPB; ++c) acc = kind[i] ? fmin(acc, sh[c][i]) : acc + sh[c][i];
+    out_blk[i] = acc;
+  }
+}
+
+template <typename T, int LPC, int APL>
+__global__ __launch_bounds__(RT_BLOCK) void k_diag(int64_t N, int K, const double *dirs, const double *W,
+                                                   double c_red, double c_light, const T *I, const double *vol,
+                                                   const double *etot, const double *mom, double *partial,
+                                                   int64_t nblk) {
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  constexpr int CPB = RT_BLOCK / LPC;
+  const int64_t cell = lb * CPB + threadIdx.x / LPC;
+  const int l = threadIdx.x % LPC;
+  double v[ND] = {0, 0, 0, 0, 0, 0, 0, 0, INFINITY, 0};
+  const int kind[ND] = {0, 0, 0, 0, 0, 0, 0, 0, 1, 0};
+  if (cell < N) {
+    rt_lane_angles<double, LPC, APL> ang;
+    ang.load(dirs, W, K, l);
+    double E = 0, Fx = 0, Fy = 0, Fz = 0, mn = INFINITY, bad = 0;
+    for (int q = 0; q < APL; ++q) {
+      if (!ang.ok[q]) continue;
+      const double x = (double)I[cell * (int64_t)K + ang.k[q]];
+      if (!isfinite(x)) bad += 1;
+      mn = fmin(mn, x);
+      E += ang.w[q] * x;
+      Fx += ang.w[q] * ang.dx[q] * x;
+      Fy += ang.w[q] * ang.dy[q] * x;
+      Fz += ang.w[q] * ang.dz[q] * x;
+    }
+    E = rt_group_sum<LPC>(E);
+    Fx = rt_group_sum<LPC>(Fx);
+    Fy = rt_group_sum<LPC>(Fy);
+    Fz = rt_group_sum<LPC>(Fz);
+    bad = rt_group_sum<LPC>(bad);
+    mn = rt_group_min<LPC>(mn);
+    const double V = vol[cell], fp = 4.0 * RT_PI;
+    const double eg = etot[cell];
+    const double m[3] = {mom[3 * cell], mom[3 * cell + 1], mom[3 * cell + 2]};
+    bad += !isfinite(eg) + !isfinite(m[0]) + !isfinite(m[1]) + !isfinite(m[2]);
+    v[0] = V * eg;
+    v[1] = V * (c_light / c_red) * fp * E;
+    v[2] = V * m[0];
+    v[3] = V * m[1];
+    v[4] = V * m[2];
+    v[5] = V * fp * Fx / c_red;
+    v[6] = V * fp * Fy / c_red;
+    v[7] = V * fp * Fz / c_red;
+    v[8] = mn;
+    v[9] = bad;
+  }
+  block_reduce_store<ND, LPC>(v, kind, partial + lb * ND);
+}
+
+__global__ __launch_bounds__(RT_BLOCK) void k_final(const double *partial, int64_t nblk, int nv,
+                                                    unsigned min_mask, double *out) {
+  // one workgroup: thread i < nv reduces column i over all partial rows in order
+  const int i = threadIdx.x;
+  if (i >= nv) return;
+  const bool is_min = (min_mask >> i) & 1u;
+  double acc = is_min ? INFINITY : 0.0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    const double x = partial[b * nv + i];
+    acc = is_min ? fmin(acc, x) : acc + x;
+  }
+  out[i] = acc;
+}
+
+// Loss: each (face, angle) belongs to its upwind cell (A n_out . n_k > 0), which adds
+// u_f sigma 4 pi c W_k (A n_out . n_k) I to its partial loss and that coefficient to
+// its seed; sigma = -1 on a face's second cell since n_out = -n_f there.
+template <typename T, int LPC, int APL>
+__global__ __launch_bounds__(RT_BLOCK) void k_loss(int64_t N, int K, const int32_t *row_ptr, const int32_t *hf_face,
+                                                   const double4 *hf_an, const double *dirs, const double *W,
+                                                   double c_light, const T *I, const double *face_weight,
+                                                   T *seed, double *partial, int64_t nblk) {
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  constexpr int CPB = RT_BLOCK / LPC;
+  const int64_t cell = lb * CPB + threadIdx.x / LPC;
+  const int l = threadIdx.x % LPC;
+  double v[1] = {0.0};
+  const int kind[1] = {0};
+  if (cell < N) {
+    rt_lane_angles<double, LPC, APL> ang;
+    ang.load(dirs, W, K, l);
+    const int64_t row = cell * (int64_t)K;
+    double sd[APL], Iv[APL];
+    for (int q = 0; q < APL; ++q) {
+      sd[q] = 0.0;
+      Iv[q] = ang.ok[q] ? (double)I[row + ang.k[q]] : 0.0;
+    }
+    const double fpc = 4.0 * RT_PI * c_light;
+    double part = 0.0;
+    for (int h = row_ptr[cell]; h < row_ptr[cell + 1]; ++h) {
+      const int32_t fc = hf_face[h];
+      const int64_t f = fc >= 0 ? fc : -(int64_t)fc - 1;
+      const double u = face_weight[f];
+      if (u == 0.0) continue;
+      const double sg = fc >= 0 ? u : -u;
+      const double4 r = hf_an[h];
+      for (int q = 0; q < APL; ++q) {
+        const double m = r.x * ang.dx[q] + r.y * ang.dy[q] + r.z * ang.dz[q];
+        if (m > 0.0) {
+          const double coef = sg * fpc * ang.w[q] * m;
+          part += coef * Iv[q];
+          sd[q] += coef;
+        }
+      }
+    }
+    if (seed)
+      for (int q = 0; q < APL; ++q)
+        if (ang.ok[q] && sd[q] != 0.0) seed[row + ang.k[q]] = (T)((double)seed[row + ang.k[q]] + sd[q]);
+    v[0] = rt_group_sum<LPC>(part);
+  }
+  block_reduce_store<1, LPC>(v, kind, partial + lb);
+}
+
+template <typename T, int LPC, int APL>
+hipError_t launch_diag(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red, double c_light,
+                       const void *I, const double *vol, const double *etot, const double *mom, double *out,
+                       hipStream_t s) {
+  const int64_t cpb = RT_BLOCK / LPC;
+  const int64_t nblk = (m->N + cpb - 1) / cpb;
+  if (nblk > m->n_red_blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_diag<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K, dirs,
+                     W, c_red, c_light, (const T *)I, vol, etot, mom, m->red, nblk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(RT_BLOCK), 0, s, m->red, nblk, ND, 1u << 8, out);
+  return hipGetLastError();
+}
+
+template <typename T, int LPC, int APL>
+hipError_t launch_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
+                       const double *fw, double *loss, void *seed, hipStream_t s) {
+  const int64_t cpb = RT_BLOCK / LPC;
+  const int64_t nblk = (m->N + cpb - 1) / cpb;
+  if (nblk > m->n_red_blocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_loss<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K,
+                     m->row_ptr, m->hf_face, m->hf_an64, dirs, W, c_light, (const T *)I, fw, (T *)seed, m->red,
+                     nblk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(RT_BLOCK), 0, s, m->red, nblk, 1, 0u, loss);
+  return hipGetLastError();
+}
+
+#define RT_DISPATCH(FN, T, ...)                                   \
+  do {                                                            \
+    if (K % 16 == 0 || K > 64) {                                  \
+      switch ((K + 15) / 16) {                                    \
+        case 1: return FN<T, 16, 1>(__VA_ARGS__);                 \
+        case 2: return FN<T, 16, 2>(__VA_ARGS__);                 \
+        case 3: return FN<T, 16, 3>(__VA_ARGS__);                 \
+        case 4: return FN<T, 16, 4>(__VA_ARGS__);                 \
+        case 5: return FN<T, 16, 5>(__VA_ARGS__);                 \
+        case 6: return FN<T, 16, 6>(__VA_ARGS__);                 \
+        case 7: return FN<T, 16, 7>(__VA_ARGS__);                 \
+        case 8: return FN<T, 16, 8>(__VA_ARGS__);                 \
+      }                                                           \
+    } else {                                                      \
+      switch ((K + 7) / 8) {                                      \
+        case 1: return FN<T, 8, 1>(__VA_ARGS__);                  \
+        case 2: return FN<T, 8, 2>(__VA_ARGS__);                  \
+        case 3: return FN<T, 8, 3>(__VA_ARGS__);                  \
+        case 4: return FN<T, 8, 4>(__VA_ARGS__);                  \
+        case 5: return FN<T, 8, 5>(__VA_ARGS__);                  \
+        case 6: return FN<T, 8, 6>(__VA_ARGS__);                  \
+        case 7: return FN<T, 8, 7>(__VA_ARGS__);                  \
+        case 8: return FN<T, 8, 8>(__VA_ARGS__);                  \
+      }                                                           \
+    }                                                             \
+    return hipErrorInvalidValue;                                  \
+  } while (0)
+
+template <typename T>
+hipError_t diag_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red, double c_light,
+                  const void *I, const double *vol, const double *etot, const double *mom, double *out,
+                  hipStream_t s) {
+  RT_DISPATCH(launch_diag, T, m, K, dirs, W, c_red, c_light, I, vol, etot, mom, out, s);
+}
+
+template <typename T>
+hipError_t loss_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
+                  const double *fw, double *loss, void *seed, hipStream_t s) {
+  RT_DISPATCH(launch_loss, T, m, K, dirs, W, c_light, I, fw, loss, seed, s);
+}
+
+}  // namespace
+
+hipError_t rt_launch_diagnostics(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red,
+                                 double c_light, const void *I, const double *vol, const double *etot,
+                                 const double *mom, double *out_dev, int dtype, hipStream_t s) {
+  return dtype == RT_F32 ? diag_t<float>(m, K, dirs, W, c_red, c_light, I, vol, etot, mom, out_dev, s)
+                         : diag_t<double>(m, K, dirs, W, c_red, c_light, I, vol, etot, mom, out_dev, s);
+}
+
+hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                               const void *I, const double *face_weight, double *loss, void *seed, int dtype,
+                               hipStream_t s) {
+  return dtype == RT_F32 ? loss_t<float>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s)
+                         : loss_t<double>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s);
+}

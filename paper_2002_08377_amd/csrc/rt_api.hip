@@ -1,0 +1,481 @@
+// Host side of the C ABI declared in rtmm.h: argument checks, mesh upload (the
+// half-face index every cell gathers through), scratch management and the launch
+// sequence of each call.  All arithmetic of the method runs in the kernels.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "rt_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(RT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define RT_HIP(call, what)                     \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename P> hipError_t dmalloc(P **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  return hipMalloc((void **)p, bytes);
+}
+
+void free_mesh_arrays(rt_mesh *m) {
+  void *ptrs[] = {m->vol0,    m->D,       m->wn,       m->row_ptr, m->hf_nbr, m->hf_face, m->hf_an64,
+                  m->hf_an32, m->hf_gp64, m->hf_rel64, m->hf_gp32, m->hf_rel32, m->I_half, m->grad,
+                  m->lam_star, m->red};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+int check_call(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
+  if (!m) return fail(RT_EINVAL, "mesh is NULL");
+  if (!p) return fail(RT_EINVAL, "params is NULL");
+  if (!a) return fail(RT_EINVAL, "angles is NULL");
+  if (a->K < 1 || a->K > m->k_max || a->K > RT_K_MAX)
+    return fail(RT_EINVAL, "K=%d outside [1, k_max=%d]", a->K, m->k_max);
+  if (!a->dir || !a->weight) return fail(RT_EINVAL, "angle arrays are NULL");
+  if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(RT_EINVAL, "dt must be positive and finite");
+  if (!(p->c_red > 0.0) || !isfinite(p->c_red)) return fail(RT_EINVAL, "c_red must be positive");
+  if (!(p->c_light >= p->c_red) || !isfinite(p->c_light)) return fail(RT_EINVAL, "c_light must be >= c_red");
+  if (!(p->a_rad >= 0.0) || !isfinite(p->a_rad)) return fail(RT_EINVAL, "a_rad must be >= 0");
+  if (!(p->cv > 0.0) || !isfinite(p->cv)) return fail(RT_EINVAL, "cv must be positive");
+  if (p->dtype != RT_F64 && p->dtype != RT_F32) return fail(RT_EINVAL, "unknown dtype %d", p->dtype);
+  if (p->scheme != RT_UPWIND1 && p->scheme != RT_PLM_VL2) return fail(RT_EINVAL, "unknown scheme %d", p->scheme);
+  return RT_OK;
+}
+
+int check_ptrs(std::initializer_list<const void *> ps) {
+  for (const void *q : ps) {
+    if (!q) return fail(RT_EINVAL, "a required device pointer is NULL");
+    if (!aligned8(q)) return fail(RT_EINVAL, "a device pointer is not 8-byte aligned");
+  }
+  return RT_OK;
+}
+
+size_t elem(int dtype) { return dtype == RT_F32 ? sizeof(float) : sizeof(double); }
+
+bool overlap(const void *a, const void *b, size_t bytes) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + bytes && y < x + bytes;
+}
+
+rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
+  rt_step_args s;
+  memset(&s, 0, sizeof s);
+  s.N = m->N;
+  s.K = a->K;
+  s.row_ptr = m->row_ptr;
+  s.hf_nbr = m->hf_nbr;
+  s.hf_an = p->dtype == RT_F32 ? (const void *)m->hf_an32 : (const void *)m->hf_an64;
+  s.hf_rel = p->dtype == RT_F32 ? (const void *)m->hf_rel32 : (const void *)m->hf_rel64;
+  s.D = m->D;
+  s.dirs = a->dir;
+  s.W = a->weight;
+  s.c_red = p->c_red;
+  s.c_light = p->c_light;
+  s.a_rad = p->a_rad;
+  s.cv = p->cv;
+  s.dt = p->dt;
+  return s;
+}
+
+// The transport part of a step; with `src` set, the source follows each stage.
+int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, double *vol,
+             const double *rho, double *mom, double *etot, const double *kP, const double *kJ, const double *ks,
+             double *T_new, bool src, hipStream_t st) {
+  rt_step_args s = base_args(m, p, a);
+  s.rho = rho;
+  s.mom = mom;
+  s.etot = etot;
+  s.kP = kP;
+  s.kJ = kJ;
+  s.ks = ks;
+  if (p->scheme == RT_UPWIND1) {
+    s.I_in = I_in;
+    s.I_out = I_out;
+    s.vol_in = vol;
+    s.vol_out = vol;
+    s.T_out = T_new;
+    s.do_transport = 1;
+    s.do_source = src;
+    s.write_gas = 1;
+    hipError_t e = rt_launch_step(s, p->dtype, st);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    return RT_OK;
+  }
+  if (!(m->flags & RT_MESH_PLM)) return fail(RT_ESTATE, "RT_PLM_VL2 needs a mesh uploaded with RT_MESH_PLM");
+  // stage 1: first-order transport and source over dt/2 into the half-step state; gas untouched
+  rt_step_args s1 = s;
+  s1.dt = 0.5 * p->dt;
+  s1.I_in = I_in;
+  s1.I_out = m->I_half;
+  s1.vol_in = vol;
+  s1.vol_out = nullptr;
+  s1.do_transport = 1;
+  s1.do_source = src;
+  s1.write_gas = 0;
+  hipError_t e = rt_launch_step(s1, p->dtype, st);
+  if (e != hipSuccess) return hip_fail(e, "stage-1 kernel launch");
+  e = rt_launch_gradient(m, a->K, m->I_half, m->grad, p->dtype, st);
+  if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+  // stage 2: reconstructed fluxes of the half-step state on the start-of-step charges, source on gas^n
+  rt_step_args s2 = s;
+  s2.I_in = I_in;
+  s2.I_half = m->I_half;
+  s2.grad = m->grad;
+  s2.I_out = I_out;
+  s2.vol_in = vol;
+  s2.vol_out = vol;
+  s2.T_out = T_new;
+  s2.do_transport = 2;
+  s2.do_source = src;
+  s2.write_gas = 1;
+  e = rt_launch_step(s2, p->dtype, st);
+  if (e != hipSuccess) return hip_fail(e, "stage-2 kernel launch");
+  return RT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rt_strerror(int code) {
+  switch (code) {
+    case RT_OK: return "ok";
+    case RT_EINVAL: return "invalid argument";
+    case RT_ENOMEM: return "out of device memory";
+    case RT_EHIP: return "HIP runtime error";
+    case RT_ENONFINITE: return "non-finite values";
+    case RT_ESTATE: return "mesh not prepared for this call";
+  }
+  return "unknown error";
+}
+
+const char *rt_last_error(void) { return g_last_error.c_str(); }
+
+int rt_version(void) { return RTMM_VERSION; }
+
+int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t flags, const double *gen,
+                   const double *com, const double *vol, const double *mesh_vel, const int32_t *face_cells,
+                   const int8_t *face_shift, const double *face_area, const double *face_normal,
+                   const double *face_centroid, double box, void *stream) {
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (N < 1 || F < 1) return fail(RT_EINVAL, "need n_cells >= 1 and n_faces >= 1");
+  if (N >= (int64_t)1 << 31 || 2 * F >= (int64_t)1 << 31) return fail(RT_EINVAL, "mesh too large for int32 indices");
+  if (k_max < 1 || k_max > RT_K_MAX) return fail(RT_EINVAL, "k_max=%d outside [1, %d]", k_max, RT_K_MAX);
+  if (flags & ~(RT_MESH_PLM | RT_MESH_ADJOINT)) return fail(RT_EINVAL, "unknown flags 0x%x", flags);
+  if (!gen || !com || !vol || !mesh_vel || !face_cells || !face_shift || !face_area || !face_normal ||
+      !face_centroid)
+    return fail(RT_EINVAL, "a mesh array is NULL");
+  if (!(box > 0.0) || !isfinite(box)) return fail(RT_EINVAL, "box must be positive");
+  for (int64_t i = 0; i < N; ++i)
+    if (!(vol[i] > 0.0) || !isfinite(vol[i])) return fail(RT_EINVAL, "cell %lld has volume <= 0", (long long)i);
+  // faces: indices, areas, normals; closure of every cell
+  std::vector<double> clo(3 * (size_t)N, 0.0);
+  std::vector<int32_t> cnt((size_t)N + 1, 0);
+  for (int64_t f = 0; f < F; ++f) {
+    const int32_t i = face_cells[2 * f], j = face_cells[2 * f + 1];
+    if (i < 0 || j < 0 || i >= N || j >= N || i == j)
+      return fail(RT_EINVAL, "face %lld has invalid cells (%d, %d)", (long long)f, i, j);
+    const double A = face_area[f];
+    if (!(A > 0.0) || !isfinite(A)) return fail(RT_EINVAL, "face %lld has area <= 0", (long long)f);
+    const double *n = &face_normal[3 * f];
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(fabs(nn - 1.0) < 1e-10)) return fail(RT_EINVAL, "face %lld normal is not unit", (long long)f);
+    for (int c = 0; c < 3; ++c) {
+      if (face_shift[3 * f + c] < -1 || face_shift[3 * f + c] > 1)
+        return fail(RT_EINVAL, "face %lld shift outside {-1,0,1}", (long long)f);
+      clo[3 * (size_t)i + c] += A * n[c];
+      clo[3 * (size_t)j + c] -= A * n[c];
+    }
+    cnt[(size_t)i + 1]++;
+    cnt[(size_t)j + 1]++;
+  }
+  for (int64_t i = 0; i < N; ++i) {
+    const double r = sqrt(clo[3 * i] * clo[3 * i] + clo[3 * i + 1] * clo[3 * i + 1] + clo[3 * i + 2] * clo[3 * i + 2]);
+    if (!(r <= 1e-8 * pow(vol[i], 2.0 / 3.0)))
+      return fail(RT_EINVAL, "cell %lld is not closed: |sum A n| = %g", (long long)i, r);
+  }
+  // half-face index grouped by cell, faces in input order within a cell
+  std::vector<int32_t> row_ptr((size_t)N + 1, 0);
+  for (int64_t i = 0; i < N; ++i) row_ptr[(size_t)i + 1] = row_ptr[(size_t)i] + cnt[(size_t)i + 1];
+  const int64_t H = 2 * F;
+  std::vector<int32_t> hf_face((size_t)H);
+  {
+    std::vector<int32_t> fill(row_ptr.begin(), row_ptr.end() - 1);
+    for (int64_t f = 0; f < F; ++f) {
+      const int32_t i = face_cells[2 * f], j = face_cells[2 * f + 1];
+      hf_face[(size_t)fill[(size_t)i]++] = (int32_t)f;
+      hf_face[(size_t)fill[(size_t)j]++] = (int32_t)(-f - 1);
+    }
+  }
+
+  rt_mesh *m = new rt_mesh;
+  memset(m, 0, sizeof *m);
+  (void)hipGetDevice(&m->device);
+  m->N = N;
+  m->F = F;
+  m->H = H;
+  m->k_max = k_max;
+  m->flags = flags;
+  m->box = box;
+  hipStream_t st = (hipStream_t)stream;
+  const bool plm = flags & RT_MESH_PLM;
+  const int64_t nred = (N + 7) / 8 + 8;  // >= blocks of any cell-parallel kernel (>= 8 cells per block)
+  m->n_red_blocks = nred;
+  hipError_t e = hipSuccess;
+#define RT_ALLOC(ptr, bytes)                         \
+  do {                                               \
+    if (e == hipSuccess) e = dmalloc(&(ptr), bytes); \
+  } while (0)
+  RT_ALLOC(m->vol0, sizeof(double) * N);
+  RT_ALLOC(m->D, sizeof(double) * N);
+  RT_ALLOC(m->wn, sizeof(double) * F);
+  RT_ALLOC(m->row_ptr, sizeof(int32_t) * (N + 1));
+  RT_ALLOC(m->hf_nbr, sizeof(int32_t) * H);
+  RT_ALLOC(m->hf_face, sizeof(int32_t) * H);
+  RT_ALLOC(m->hf_an64, sizeof(double4) * H);
+  RT_ALLOC(m->hf_an32, sizeof(float4) * H);
+  if (plm) {
+    RT_ALLOC(m->hf_gp64, sizeof(double4) * 2 * H);
+    RT_ALLOC(m->hf_rel64, sizeof(double4) * 2 * H);
+    RT_ALLOC(m->hf_gp32, sizeof(float4) * 2 * H);
+    RT_ALLOC(m->hf_rel32, sizeof(float4) * 2 * H);
+    RT_ALLOC(m->I_half, sizeof(double) * N * k_max);
+    RT_ALLOC(m->grad, sizeof(double) * 3 * N * k_max);
+  }
+  if (flags & RT_MESH_ADJOINT) RT_ALLOC(m->lam_star, sizeof(double) * N * k_max);
+  RT_ALLOC(m->red, sizeof(double) * RT_NDIAG * nred);
+  // temporaries of the upload
+  double *d_gen = nullptr, *d_com = nullptr, *d_w = nullptr, *d_area = nullptr, *d_nrm = nullptr, *d_cen = nullptr;
+  int32_t *d_fc = nullptr;
+  int8_t *d_shift = nullptr;
+  RT_ALLOC(d_gen, sizeof(double) * 3 * N);
+  RT_ALLOC(d_com, sizeof(double) * 3 * N);
+  RT_ALLOC(d_w, sizeof(double) * 3 * N);
+  RT_ALLOC(d_area, sizeof(double) * F);
+  RT_ALLOC(d_nrm, sizeof(double) * 3 * F);
+  RT_ALLOC(d_cen, sizeof(double) * 3 * F);
+  RT_ALLOC(d_fc, sizeof(int32_t) * 2 * F);
+  RT_ALLOC(d_shift, 3 * F);
+#undef RT_ALLOC
+  auto cleanup_tmp = [&]() {
+    void *t[] = {d_gen, d_com, d_w, d_area, d_nrm, d_cen, d_fc, d_shift};
+    for (void *p : t)
+      if (p) (void)hipFree(p);
+  };
+  if (e != hipSuccess) {
+    cleanup_tmp();
+    free_mesh_arrays(m);
+    delete m;
+    return fail(RT_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  auto H2D = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  H2D(m->vol0, vol, sizeof(double) * N);
+  H2D(m->row_ptr, row_ptr.data(), sizeof(int32_t) * (N + 1));
+  H2D(m->hf_face, hf_face.data(), sizeof(int32_t) * H);
+  H2D(d_gen, gen, sizeof(double) * 3 * N);
+  H2D(d_com, com, sizeof(double) * 3 * N);
+  H2D(d_w, mesh_vel, sizeof(double) * 3 * N);
+  H2D(d_area, face_area, sizeof(double) * F);
+  H2D(d_nrm, face_normal, sizeof(double) * 3 * F);
+  H2D(d_cen, face_centroid, sizeof(double) * 3 * F);
+  H2D(d_fc, face_cells, sizeof(int32_t) * 2 * F);
+  H2D(d_shift, face_shift, 3 * F);
+  if (e == hipSuccess) e = rt_launch_face_speed(d_gen, d_w, d_fc, d_shift, d_nrm, d_cen, box, F, m->wn, st);
+  if (e == hipSuccess) e = rt_launch_half_faces(m, d_fc, d_area, d_nrm, d_cen, d_gen, d_com, d_shift, st);
+  if (e == hipSuccess) e = rt_launch_volume_rate(m, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup_tmp();
+  if (e != hipSuccess) {
+    free_mesh_arrays(m);
+    delete m;
+    return hip_fail(e, "mesh upload");
+  }
+  *out = m;
+  return RT_OK;
+}
+
+int rt_mesh_free(rt_mesh *m) {
+  if (!m) return RT_OK;
+  (void)hipDeviceSynchronize();
+  free_mesh_arrays(m);
+  delete m;
+  return RT_OK;
+}
+
+int rt_mesh_info(const rt_mesh *m, int64_t *n_cells, int64_t *n_faces, int64_t *n_half, int32_t *k_max,
+                 int32_t *flags) {
+  if (!m) return fail(RT_EINVAL, "mesh is NULL");
+  if (n_cells) *n_cells = m->N;
+  if (n_faces) *n_faces = m->F;
+  if (n_half) *n_half = m->H;
+  if (k_max) *k_max = m->k_max;
+  if (flags) *flags = m->flags;
+  return RT_OK;
+}
+
+int rt_mesh_geometry(const rt_mesh *m, double *face_speed, double *vol_rate, void *stream) {
+  if (!m) return fail(RT_EINVAL, "mesh is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (face_speed)
+    RT_HIP(hipMemcpyAsync(face_speed, m->wn, sizeof(double) * m->F, hipMemcpyDeviceToDevice, st), "copy wn");
+  if (vol_rate)
+    RT_HIP(hipMemcpyAsync(vol_rate, m->D, sizeof(double) * m->N, hipMemcpyDeviceToDevice, st), "copy D");
+  return RT_OK;
+}
+
+int rt_transport_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out,
+                      double *vol, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I_in, I_out, vol}))) return rc;
+  if (overlap(I_in, I_out, elem(p->dtype) * m->N * a->K)) return fail(RT_EINVAL, "I_in and I_out overlap");
+  return run_step(m, p, a, I_in, I_out, vol, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false,
+                  (hipStream_t)stream);
+}
+
+int rt_source_implicit(rt_mesh *m, const rt_params *p, const rt_angles *a, void *I, const double *rho,
+                       double *mom, double *etot, const double *kP, const double *kJ, const double *ks,
+                       double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, rho, mom, etot, kP, kJ, ks}))) return rc;
+  rt_step_args s = base_args(m, p, a);
+  s.I_in = I;
+  s.I_out = I;
+  s.rho = rho;
+  s.mom = mom;
+  s.etot = etot;
+  s.kP = kP;
+  s.kJ = kJ;
+  s.ks = ks;
+  s.T_out = T_new;
+  s.do_transport = 0;
+  s.do_source = 1;
+  s.write_gas = 1;
+  hipError_t e = rt_launch_step(s, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "source kernel launch");
+  return RT_OK;
+}
+
+int rt_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, double *vol,
+            const double *rho, double *mom, double *etot, const double *kP, const double *kJ, const double *ks,
+            double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I_in, I_out, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
+  if (overlap(I_in, I_out, elem(p->dtype) * m->N * a->K)) return fail(RT_EINVAL, "I_in and I_out overlap");
+  return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream);
+}
+
+int rt_gradient(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, void *grad, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, grad}))) return rc;
+  if (!(m->flags & RT_MESH_PLM)) return fail(RT_ESTATE, "rt_gradient needs a mesh uploaded with RT_MESH_PLM");
+  hipError_t e = rt_launch_gradient(m, a->K, I, grad, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+  return RT_OK;
+}
+
+int rt_step_adjoint(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_star, const double *vol_n,
+                    const double *rho, const double *mom_n, const double *etot_n, const double *kP,
+                    const double *kJ, const double *ks, void *lamI, double *lamE, double *lamM, double *dkP,
+                    double *dkJ, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I_star, vol_n, rho, mom_n, etot_n, kP, kJ, ks, lamI, lamE, lamM}))) return rc;
+  if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "the adjoint covers RT_UPWIND1 steps only");
+  if (!(m->flags & RT_MESH_ADJOINT)) return fail(RT_ESTATE, "rt_step_adjoint needs RT_MESH_ADJOINT");
+  rt_adj_args s;
+  memset(&s, 0, sizeof s);
+  s.N = m->N;
+  s.K = a->K;
+  s.row_ptr = m->row_ptr;
+  s.hf_nbr = m->hf_nbr;
+  s.hf_an = p->dtype == RT_F32 ? (const void *)m->hf_an32 : (const void *)m->hf_an64;
+  s.D = m->D;
+  s.dirs = a->dir;
+  s.W = a->weight;
+  s.I_star = I_star;
+  s.vol_n = vol_n;
+  s.rho = rho;
+  s.mom = mom_n;
+  s.etot = etot_n;
+  s.kP = kP;
+  s.kJ = kJ;
+  s.ks = ks;
+  s.lamI = lamI;
+  s.lam_star = m->lam_star;
+  s.lamE = lamE;
+  s.lamM = lamM;
+  s.dkP = dkP;
+  s.dkJ = dkJ;
+  s.c_red = p->c_red;
+  s.c_light = p->c_light;
+  s.a_rad = p->a_rad;
+  s.cv = p->cv;
+  s.dt = p->dt;
+  hipError_t e = rt_launch_adjoint(s, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+  return RT_OK;
+}
+
+int rt_flux_loss(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, const double *face_weight,
+                 double *loss, void *seed, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, face_weight, loss}))) return rc;
+  if (seed && !aligned8(seed)) return fail(RT_EINVAL, "seed is not 8-byte aligned");
+  hipError_t e = rt_launch_flux_loss(m, a->K, a->dir, a->weight, p->c_light, I, face_weight, loss, seed, p->dtype,
+                                     (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "loss kernel launch");
+  return RT_OK;
+}
+
+int rt_diagnostics(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, const double *vol,
+                   const double *etot, const double *mom, double *out, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, vol, etot, mom}))) return rc;
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  double *dout = m->red + (m->n_red_blocks - 1) * RT_NDIAG;  // last row of the partials, unused by the kernels
+  hipError_t e = rt_launch_diagnostics(m, a->K, a->dir, a->weight, p->c_red, p->c_light, I, vol, etot, mom, dout,
+                                       p->dtype, st);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics kernel launch");
+  RT_HIP(hipMemcpyAsync(out, dout, sizeof(double) * RT_NDIAG, hipMemcpyDeviceToHost, st), "copy diagnostics");
+  RT_HIP(hipStreamSynchronize(st), "synchronise diagnostics");
+  if (out[9] != 0.0) return fail(RT_ENONFINITE, "%g non-finite values", out[9]);
+  return RT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Device-side helpers shared by the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rt_internal.h"
+
+#define RT_PI 3.14159265358979323846
+
+// Half-face record type of a precision.
+template <typename T> struct rt_vec4;
+template <> struct rt_vec4<double> { using type = double4; };
+template <> struct rt_vec4<float> { using type = float4; };
+
+// MI355X has 8 XCDs, each with its own L2; consecutive workgroups are dispatched
+// round-robin over them.  The grid is padded to a multiple of 8 and workgroup b
+// takes logical tile (b % 8) * per + b / 8, so every XCD sweeps one contiguous
+// range of cells (cells are numbered along a space-filling curve, so its
+// neighbour rows stay in that XCD's L2).  Returns -1 for padding workgroups.
+__device__ __forceinline__ int64_t rt_logical_block(int64_t nblk) {
+  const int64_t per = (nblk + 7) / 8;
+  const int64_t b = blockIdx.x;
+  const int64_t L = (b % 8) * per + b / 8;
+  return L < nblk ? L : -1;
+}
+
+static inline int64_t rt_grid_for(int64_t nblk) { return ((nblk + 7) / 8) * 8; }
+
+// Sum over the LPC lanes of a cell group.  The xor butterfly leaves bit-identical
+// totals in every lane of the group (each pairwise add is commutative).
+template <int LPC> __device__ __forceinline__ double rt_group_sum(double v) {
+#pragma unroll
+  for (int o = LPC / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPC);
+  return v;
+}
+template <int LPC> __device__ __forceinline__ double rt_group_min(double v) {
+#pragma unroll
+  for (int o = LPC / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, LPC));
+  return v;
+}
+
+// Unique positive root of A T^4 + B T - C = 0 (A >= 0; B, C > 0).  Newton from
+// T0 = min((C/A)^(1/4), C/B): f(T0) >= 0 and f is convex and increasing for
+// T > 0, so the iterates fall monotonically; stop at the first one that does not.
+__device__ __forceinline__ double rt_quartic_root(double A, double B, double C) {
+  if (!(A > 0.0)) return C / B;
+  double T = fmin(sqrt(sqrt(C / A)), C / B);
+  for (int it = 0; it < 100; ++it) {
+    const double T3 = T * T * T;
+    const double Tn = T - (A * T3 * T + B * T - C) / (4.0 * A * T3 + B);
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
+// Angles of a lane: k = l + LPC * q for q < APL; ok[q] false past K.
+template <typename T, int LPC, int APL> struct rt_lane_angles {
+  T dx[APL], dy[APL], dz[APL];
+  double w[APL];
+  int k[APL];
+  bool ok[APL];
+  __device__ __forceinline__ void load(const double *dirs, const double *W, int K, int l) {
+#pragma unroll
+    for (int q = 0; q < APL; ++q) {
+      const int kk = l + LPC * q;
+      ok[q] = kk < K;
+      k[q] = ok[q] ? kk : 0;
+      dx[q] = (T)dirs[3 * k[q]];
+      dy[q] = (T)dirs[3 * k[q] + 1];
+      dz[q] = (T)dirs[3 * k[q] + 2];
+      w[q] = ok[q] ? W[k[q]] : 0.0;
+    }
+  }
+};

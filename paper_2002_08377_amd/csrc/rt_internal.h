@@ -1,0 +1,115 @@
+// Internal declarations shared by the host side of the C ABI and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtmm.h"
+
+// Threads per workgroup of every cell-parallel kernel (four 64-wide waves).
+#define RT_BLOCK 256
+
+struct rt_mesh {
+  int device;
+  int64_t N, F, H;  // cells, faces, half-faces (= 2F)
+  int32_t k_max, flags;
+  double box;
+  // geometry resident on the device
+  double *vol0;       // [N] geometric volumes (gradient estimator)
+  double *D;          // [N] volume rate sum_faces A (w~.n), outward positive
+  double *wn;         // [F] face normal speed w~.n
+  int32_t *row_ptr;   // [N+1] half-faces of cell i are [row_ptr[i], row_ptr[i+1])
+  int32_t *hf_nbr;    // [H] the other cell of each half-face
+  int32_t *hf_face;   // [H] face id f for the face's first cell, -(f+1) for its second
+  double4 *hf_an64;   // [H] (A n_out, A (w~.n)_out), FP64
+  float4 *hf_an32;    // [H] same, FP32
+  // reconstruction geometry (RT_MESH_PLM): per half-face, from the owning cell's side
+  double4 *hf_gp64;   // [H][2]: (A c/d, A/2 n_out.x), (A/2 n_out.y, A/2 n_out.z, -, -)
+  double4 *hf_rel64;  // [H][2]: (r~ - s_self, r~ - s_nbr.x), (r~ - s_nbr.y, .z, -, -)
+  float4 *hf_gp32;
+  float4 *hf_rel32;
+  // scratch
+  void *I_half;       // [N][k_max] doubles (RT_MESH_PLM), used in either precision
+  void *grad;         // [N][3][k_max] doubles (RT_MESH_PLM)
+  void *lam_star;     // [N][k_max] doubles (RT_MESH_ADJOINT)
+  double *red;        // reduction partials, RT_NDIAG * n_red_blocks doubles
+  int64_t n_red_blocks;
+};
+
+// ------------------------------------------------------------------------------------------
+// launch helpers implemented in the kernel files; all return hipError_t of the launch
+// ------------------------------------------------------------------------------------------
+
+struct rt_step_args {
+  int64_t N;
+  int K;
+  const int32_t *row_ptr;
+  const int32_t *hf_nbr;
+  const void *hf_an;   // double4* or float4*
+  const void *hf_rel;  // PLM only
+  const double *D;
+  const double *dirs;
+  const double *W;
+  const void *I_in;    // intensities read by transport (start-of-step charges)
+  const void *I_half;  // PLM stage 2: half-step intensities (face states)
+  const void *grad;    // PLM stage 2: limited gradients of I_half
+  void *I_out;
+  const double *vol_in;
+  double *vol_out;
+  const double *rho;
+  double *mom;
+  double *etot;
+  const double *kP;
+  const double *kJ;
+  const double *ks;
+  double *T_out;
+  double c_red, c_light, a_rad, cv, dt;
+  int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2)
+  int do_source;
+  int write_gas;
+};
+
+hipError_t rt_launch_face_speed(const double *gen, const double *mesh_vel, const int32_t *face_cells,
+                                const int8_t *face_shift, const double *face_normal, const double *face_centroid,
+                                double box, int64_t F, double *wn, hipStream_t s);
+hipError_t rt_launch_half_faces(rt_mesh *m, const int32_t *face_cells, const double *face_area,
+                                const double *face_normal, const double *face_centroid, const double *gen,
+                                const double *com, const int8_t *face_shift, hipStream_t s);
+hipError_t rt_launch_volume_rate(rt_mesh *m, hipStream_t s);
+
+hipError_t rt_launch_step(const rt_step_args &a, int dtype, hipStream_t s);
+hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, hipStream_t s);
+
+struct rt_adj_args {
+  int64_t N;
+  int K;
+  const int32_t *row_ptr;
+  const int32_t *hf_nbr;
+  const void *hf_an;
+  const double *D;
+  const double *dirs;
+  const double *W;
+  const void *I_star;
+  const double *vol_n;
+  const double *rho;
+  const double *mom;
+  const double *etot;
+  const double *kP;
+  const double *kJ;
+  const double *ks;
+  void *lamI;       // in: dL/dI^{n+1}; out: dL/dI^n
+  void *lam_star;   // scratch: dL/dI*
+  double *lamE;
+  double *lamM;
+  double *dkP;
+  double *dkJ;
+  double c_red, c_light, a_rad, cv, dt;
+};
+hipError_t rt_launch_adjoint(const rt_adj_args &a, int dtype, hipStream_t s);
+
+hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                               const void *I, const double *face_weight, double *loss, void *seed, int dtype,
+                               hipStream_t s);
+hipError_t rt_launch_diagnostics(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red,
+                                 double c_light, const void *I, const double *vol, const double *etot,
+                                 const double *mom, double *out_dev, int dtype, hipStream_t s);

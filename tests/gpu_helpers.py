@@ -1,0 +1,62 @@
+"""Shared set-up for the GPU parity tests: seeded problems on the device and in the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle as orc
+from paper_2002_08377_amd import inputs as inp
+from paper_2002_08377_amd import rt
+
+
+def rel_err(a, b):
+    """Normwise relative error max|a - b| / max|b|."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+class DeviceProblem:
+    """A seeded problem uploaded to the library, plus its oracle twin."""
+
+    def __init__(self, prob: inp.Problem, dtype=rt.F64, scheme=rt.UPWIND1, flags=0):
+        self.p = prob
+        st = prob.state
+        self.dtype = dtype
+        self.scheme = scheme
+        self.mesh = rt.Mesh.from_inputs(prob.mesh, st.mesh_vel, k_max=prob.dirs.shape[0],
+                                        flags=flags | (rt.MESH_PLM if scheme == rt.PLM_VL2 else 0))
+        self.angles = rt.AngleSet(prob.dirs, prob.weights)
+        ph = prob.phys
+        self.params = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, prob.dt, dtype, scheme)
+        d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+        td = rt.torch_dtype(dtype)
+        self.I = torch.as_tensor(st.I, device="cuda").to(td).contiguous()
+        self.I2 = torch.empty_like(self.I)
+        self.vol = d(st.vol)
+        self.rho, self.mom, self.etot = d(st.rho), d(st.mom), d(st.etot)
+        self.kP, self.kJ, self.ks = d(st.kP), d(st.kJ), d(st.ks)
+        self.T = torch.zeros_like(self.rho)
+        self.om = orc.OracleMesh(prob.mesh, st.mesh_vel)
+
+    def oracle_state(self):
+        st = self.p.state
+        return orc.OState(st.I, st.vol, st.mom, st.etot)
+
+    def gpu_step(self):
+        rt.step(self.mesh, self.params, self.angles, self.I, self.I2, self.vol, self.rho, self.mom, self.etot,
+                self.kP, self.kJ, self.ks, self.T)
+        self.I, self.I2 = self.I2, self.I
+
+    def run_gpu(self, steps):
+        for _ in range(steps):
+            self.gpu_step()
+        torch.cuda.synchronize()
+
+    def run_oracle(self, steps, scheme="upwind1"):
+        st = self.p.state
+        return orc.run(self.om, self.p.dirs, self.p.weights, self.p.phys, self.p.dt, self.oracle_state(), st.rho,
+                       st.kP, st.kJ, st.ks, steps, scheme)
+
+    def host(self, t):
+        return t.double().cpu().numpy()

@@ -1,0 +1,71 @@
+"""The C ABI without a GPU: the library loads, exports every function rtmm.h declares,
+and rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2002_08377_amd import rt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rtmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_function_is_exported():
+    names = _declared()
+    assert len(names) >= 14
+    L = rt.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version_and_strerror():
+    L = rt.lib()
+    assert L.rt_version() == 1
+    assert L.rt_strerror(rt.RT_EINVAL) == b"invalid argument"
+    assert L.rt_strerror(12345) == b"unknown error"
+
+
+def test_upload_rejects_bad_meshes_on_the_host():
+    L = rt.lib()
+    out = ctypes.c_void_p()
+    rc = L.rt_mesh_upload(ctypes.byref(out), 0, 0, 8, 0, *([None] * 9), 1.0, None)
+    assert rc == rt.RT_EINVAL and out.value is None
+    assert b"n_cells" in L.rt_last_error()
+    # a two-cell "mesh" whose faces do not close
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    gen = np.zeros((2, 3)); com = np.zeros((2, 3)); vol = np.ones(2); w = np.zeros((2, 3))
+    fc = np.array([[0, 1]], dtype=np.int32); fs = np.zeros((1, 3), dtype=np.int8)
+    fa = np.ones(1); fn = np.array([[1.0, 0, 0]]); fcen = np.zeros((1, 3))
+    rc = L.rt_mesh_upload(ctypes.byref(out), 2, 1, 8, 0, p(gen), p(com), p(vol), p(w), p(fc), p(fs), p(fa), p(fn),
+                          p(fcen), 1.0, None)
+    assert rc == rt.RT_EINVAL and b"not closed" in L.rt_last_error()
+    fc_bad = np.array([[0, 2]], dtype=np.int32)
+    rc = L.rt_mesh_upload(ctypes.byref(out), 2, 1, 8, 0, p(gen), p(com), p(vol), p(w), p(fc_bad), p(fs), p(fa),
+                          p(fn), p(fcen), 1.0, None)
+    assert rc == rt.RT_EINVAL and b"invalid cells" in L.rt_last_error()
+    rc = L.rt_mesh_upload(ctypes.byref(out), 2, 1, 500, 0, p(gen), p(com), p(vol), p(w), p(fc), p(fs), p(fa),
+                          p(fn), p(fcen), 1.0, None)
+    assert rc == rt.RT_EINVAL and b"k_max" in L.rt_last_error()
+
+
+def test_calls_reject_null_mesh():
+    L = rt.lib()
+    prm = rt.make_params(1.0, 1.0, 1.0, 1.5, 0.1)
+    rc = L.rt_step(None, ctypes.byref(prm), None, *([None] * 11))
+    assert rc == rt.RT_EINVAL
+    assert L.rt_mesh_free(None) == rt.RT_OK
+
+
+def test_params_layout_matches_header():
+    # c_red, c_light, a_rad, cv, dt (5 doubles) then dtype, scheme (2 int32)
+    assert ctypes.sizeof(rt.Params) == 48
+    assert rt.Params.dtype.offset == 40 and rt.Params.scheme.offset == 44
+    assert ctypes.sizeof(rt._Angles) == 24 and rt._Angles.dir.offset == 8
