@@ -23,6 +23,9 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # fuse a*b+c only within one source expression, so every instantiation of a kernel
+    # rounds the same way
+    "-ffp-contract=on",
     # no packed FP32 (v_pk_*_f32) instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-variable", "-Wno-unused-command-line-argument",

@@ -77,16 +77,25 @@ __global__ __launch_bounds__(RT_BLOCK) void k_diag(int64_t N, int K, const doubl
 
 __global__ __launch_bounds__(RT_BLOCK) void k_final(const double *partial, int64_t nblk, int nv,
                                                     unsigned min_mask, double *out) {
-  // one workgroup: thread i < nv reduces column i over all partial rows in order
-  const int i = threadIdx.x;
-  if (i >= nv) return;
-  const bool is_min = (min_mask >> i) & 1u;
-  double acc = is_min ? INFINITY : 0.0;
-  for (int64_t b = 0; b < nblk; ++b) {
-    const double x = partial[b * nv + i];
-    acc = is_min ? fmin(acc, x) : acc + x;
+  // one workgroup; column i: thread t folds rows t, t + 256, ... in order, then a fixed tree in LDS
+  __shared__ double sh[RT_BLOCK];
+  const int t = threadIdx.x;
+  for (int i = 0; i < nv; ++i) {
+    const bool is_min = (min_mask >> i) & 1u;
+    double acc = is_min ? INFINITY : 0.0;
+    for (int64_t b = t; b < nblk; b += RT_BLOCK) {
+      const double x = partial[b * nv + i];
+      acc = is_min ? fmin(acc, x) : acc + x;
+    }
+    sh[t] = acc;
+    __syncthreads();
+    for (int o = RT_BLOCK / 2; o > 0; o >>= 1) {
+      if (t < o) sh[t] = is_min ? fmin(sh[t], sh[t + o]) : sh[t] + sh[t + o];
+      __syncthreads();
+    }
+    if (t == 0) out[i] = sh[0];
+    __syncthreads();
   }
-  out[i] = acc;
 }
 
 // Loss: each (face, angle) belongs to its upwind cell (A n_out . n_k > 0), which adds

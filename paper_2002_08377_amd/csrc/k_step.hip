@@ -8,9 +8,18 @@
 
 namespace {
 
-template <typename T, int LPC, int APL>
+// Faces gathered per batch: all their neighbour-row loads are issued before any is
+// used, so one memory round trip serves U faces.
+template <typename T> struct rt_batch { static constexpr int U = 4; };
+template <> struct rt_batch<double> { static constexpr int U = 2; };
+
+// MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
+// transport of PLM stage 2 (+ source).  Separate instantiations keep each one's
+// registers to what its own loop needs.
+template <typename T, int LPC, int APL, int MODE>
 __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
+  constexpr int U = rt_batch<T>::U;
   const int64_t lb = rt_logical_block(nblk);
   if (lb < 0) return;
   constexpr int CPB = RT_BLOCK / LPC;
@@ -25,10 +34,10 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   const int64_t row = cell * (int64_t)K;
   T Ic[APL];
 #pragma unroll
-  for (int q = 0; q < APL; ++q) Ic[q] = ang.ok[q] ? Iin[row + ang.k[q]] : T(0);
+  for (int q = 0; q < APL; ++q) Ic[q] = Iin[row + ang.k[q]];
 
   double Vnew = 0.0;
-  if (a.do_transport) {
+  if (MODE != 0) {
     // ---- transport: charges V I minus the upwind charge through every face -------------
     const double Vn = a.vol_in[cell];
     Vnew = Vn + a.dt * a.D[cell];
@@ -38,18 +47,33 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
     const V4 *an = (const V4 *)a.hf_an;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
-    if (a.do_transport == 1) {
-      for (int h = h0; h < h1; ++h) {
-        const int64_t j = a.hf_nbr[h];
-        const V4 r = an[h];
-        // g = dt (cbar (A n_out).n_k - A (w~.n)_out): charge leaving through the face per unit I_up
-        const T ax = sc * r.x, ay = sc * r.y, az = sc * r.z, b = sd * r.w;
-        const T *Ij = Iin + j * K;
+    if (MODE == 1) {
+      for (int h = h0; h < h1; h += U) {
+        // batch metadata; slots past the cell's last face read face h0 with a zero record
+        int64_t j[U];
+        V4 r[U];
 #pragma unroll
-        for (int q = 0; q < APL; ++q) {
-          const T g = ax * ang.dx[q] + ay * ang.dy[q] + az * ang.dz[q] - b;
-          const T vj = ang.ok[q] ? Ij[ang.k[q]] : T(0);
-          acc[q] -= g * (g > T(0) ? Ic[q] : vj);
+        for (int u = 0; u < U; ++u) {
+          const bool v = h + u < h1;
+          const int hc = v ? h + u : h0;
+          j[u] = a.hf_nbr[hc];
+          r[u] = an[hc];
+          if (!v) r[u] = V4{T(0), T(0), T(0), T(0)};
+        }
+        T x[U][APL];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < APL; ++q) x[u][q] = Iin[j[u] * K + ang.k[q]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          // g = dt (cbar (A n_out).n_k - A (w~.n)_out): charge leaving per unit upwind intensity
+          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, b = sd * r[u].w;
+#pragma unroll
+          for (int q = 0; q < APL; ++q) {
+            const T g = ax * ang.dx[q] + ay * ang.dy[q] + az * ang.dz[q] - b;
+            acc[q] -= g * (g > T(0) ? Ic[q] : x[u][q]);
+          }
         }
       }
     } else {
@@ -66,20 +90,44 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
         gsy[q] = G[(cell * 3 + 1) * K + k];
         gsz[q] = G[(cell * 3 + 2) * K + k];
       }
-      for (int h = h0; h < h1; ++h) {
-        const int64_t j = a.hf_nbr[h];
-        const V4 r = an[h];
-        const V4 r0 = rel[2 * h], r1 = rel[2 * h + 1];
-        const T ax = sc * r.x, ay = sc * r.y, az = sc * r.z, b = sd * r.w;
-        const T *Hj = Ih + j * K;
-        const T *Gj = G + j * 3 * K;
+      constexpr int UP = sizeof(T) == 4 ? 2 : 1;
+      for (int h = h0; h < h1; h += UP) {
+        int64_t j[UP];
+        V4 r[UP], r0[UP], r1[UP];
 #pragma unroll
-        for (int q = 0; q < APL; ++q) {
-          const int k = ang.k[q];
-          const T g = ax * ang.dx[q] + ay * ang.dy[q] + az * ang.dz[q] - b;
-          const T fs = hs[q] + gsx[q] * r0.x + gsy[q] * r0.y + gsz[q] * r0.z;
-          const T fn = Hj[k] + Gj[k] * r0.w + Gj[K + k] * r1.x + Gj[2 * K + k] * r1.y;
-          acc[q] -= g * (g > T(0) ? fs : fn);
+        for (int u = 0; u < UP; ++u) {
+          const bool v = h + u < h1;
+          const int hc = v ? h + u : h0;
+          j[u] = a.hf_nbr[hc];
+          r[u] = an[hc];
+          r0[u] = rel[2 * hc];
+          r1[u] = rel[2 * hc + 1];
+          if (!v) r[u] = V4{T(0), T(0), T(0), T(0)};
+        }
+        T xh[UP][APL], xg0[UP][APL], xg1[UP][APL], xg2[UP][APL];
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          const T *Hj = Ih + j[u] * K;
+          const T *Gj = G + j[u] * 3 * K;
+#pragma unroll
+          for (int q = 0; q < APL; ++q) {
+            const int k = ang.k[q];
+            xh[u][q] = Hj[k];
+            xg0[u][q] = Gj[k];
+            xg1[u][q] = Gj[K + k];
+            xg2[u][q] = Gj[2 * K + k];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UP; ++u) {
+          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, b = sd * r[u].w;
+#pragma unroll
+          for (int q = 0; q < APL; ++q) {
+            const T g = ax * ang.dx[q] + ay * ang.dy[q] + az * ang.dz[q] - b;
+            const T fs = hs[q] + gsx[q] * r0[u].x + gsy[q] * r0[u].y + gsz[q] * r0[u].z;
+            const T fn = xh[u][q] + xg0[u][q] * r0[u].w + xg1[u][q] * r1[u].x + xg2[u][q] * r1[u].y;
+            acc[q] -= g * (g > T(0) ? fs : fn);
+          }
         }
       }
     }
@@ -101,7 +149,10 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     const double chi = kJ + ks;
     const T tg = (T)gam, tvx = (T)(vx / c), tvy = (T)(vy / c), tvz = (T)(vz / c), tyc = (T)(y * chi);
     double sE = 0, sFx = 0, sFy = 0, sFz = 0, sQ = 0, s1 = 0, sG = 0, sI = 0;
-    T Gm[APL], Ico[APL], rr[APL];
+    // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
+    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S, so pass 2 keeps
+    // only Ir = I r and Br = r / Gamma^3.
+    T Br[APL];
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
       const double Id = (double)Ic[q];
@@ -111,15 +162,17 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
       sFy += wq * (double)ang.dy[q] * Id;
       sFz += wq * (double)ang.dz[q] * Id;
       const T G = tg * (T(1) - (tvx * ang.dx[q] + tvy * ang.dy[q] + tvz * ang.dz[q]));
+      const T iG = rt_rcp(G);
+      const T iG2 = iG * iG;
       const T G2 = G * G;
-      Gm[q] = G;
-      Ico[q] = G2 * G2 * Ic[q];
-      rr[q] = T(1) / (T(1) + tyc * G);
-      const double qk = wq / (double)G2;
+      const T r = rt_rcp(T(1) + tyc * G);
+      const double qk = wq * (double)iG2;
       sQ += qk;
-      s1 += qk * (double)rr[q];
-      sG += qk * (double)(G * rr[q]);
-      sI += qk * (double)(Ico[q] * rr[q]);
+      s1 += qk * (double)r;
+      sG += qk * (double)(G * r);
+      sI += qk * (double)(G2 * G2 * Ic[q] * r);
+      Ic[q] *= r;
+      Br[q] = r * iG2 * iG;
     }
     sE = rt_group_sum<LPC>(sE);
     sFx = rt_group_sum<LPC>(sFx);
@@ -145,8 +198,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     double tE = 0, tFx = 0, tFy = 0, tFz = 0;
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
-      const T G2 = Gm[q] * Gm[q];
-      const T out = ang.ok[q] ? (Ico[q] + Gm[q] * ySrc) * rr[q] / (G2 * G2) : T(0);
+      const T out = Ic[q] + Br[q] * ySrc;
       Ic[q] = out;
       const double od = (double)out;
       const double wq = ang.w[q];
@@ -175,13 +227,19 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
 #pragma unroll
   for (int q = 0; q < APL; ++q)
     if (ang.ok[q]) Iout[row + ang.k[q]] = Ic[q];
-  if (a.do_transport && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
+  if (MODE != 0 && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
 }
 
 template <typename T, int LPC, int APL> hipError_t launch(const rt_step_args &a, hipStream_t s) {
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (a.N + cpb - 1) / cpb;
-  hipLaunchKernelGGL((k_step<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, a, nblk);
+  const dim3 grid((unsigned)rt_grid_for(nblk)), block(RT_BLOCK);
+  switch (a.do_transport) {
+    case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0>), grid, block, 0, s, a, nblk); break;
+    case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1>), grid, block, 0, s, a, nblk); break;
+    case 2: hipLaunchKernelGGL((k_step<T, LPC, APL, 2>), grid, block, 0, s, a, nblk); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -55,6 +55,17 @@ __device__ __forceinline__ double rt_quartic_root(double A, double B, double C) 
   return T;
 }
 
+// Reciprocals for per-angle arithmetic.  FP64: the hardware estimate refined by
+// two Newton steps (within an ulp of 1/x); FP32: the hardware estimate (1 ulp).
+__device__ __forceinline__ double rt_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rt_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Angles of a lane: k = l + LPC * q for q < APL; ok[q] false past K.
 template <typename T, int LPC, int APL> struct rt_lane_angles {
   T dx[APL], dy[APL], dz[APL];
@@ -67,6 +78,7 @@ template <typename T, int LPC, int APL> struct rt_lane_angles {
       const int kk = l + LPC * q;
       ok[q] = kk < K;
       k[q] = ok[q] ? kk : 0;
+      // angles past K alias angle 0: loads stay in bounds, their weight is 0 and they are never stored
       dx[q] = (T)dirs[3 * k[q]];
       dy[q] = (T)dirs[3 * k[q] + 1];
       dz[q] = (T)dirs[3 * k[q] + 2];
