@@ -11,23 +11,51 @@ namespace {
 // Faces gathered per batch: all their neighbour-row loads are issued before any is
 // used, so one memory round trip serves U faces.
 template <typename T> struct rt_batch { static constexpr int U = 4; };
-template <> struct rt_batch<double> { static constexpr int U = 2; };
+template <> struct rt_batch<double> { static constexpr int U = 4; };
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
 // transport of PLM stage 2 (+ source).  Separate instantiations keep each one's
-// registers to what its own loop needs.
-template <typename T, int LPC, int APL, int MODE>
+// registers to what its own loop needs.  FULL: K == LPC * APL, so every lane angle
+// is live and k = l + LPC q needs no clamping.
+//
+// The cells of a workgroup are consecutive, so their half-faces form one contiguous
+// range; it is staged in LDS (dynamic size: the largest range of any workgroup,
+// found at upload) and the face loops read their records from there.
+template <typename T, int LPC, int APL, int MODE, bool FULL>
 __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
   constexpr int U = rt_batch<T>::U;
-  const int64_t lb = rt_logical_block(nblk);
-  if (lb < 0) return;
   constexpr int CPB = RT_BLOCK / LPC;
-  const int64_t cell = lb * CPB + threadIdx.x / LPC;
-  if (cell >= a.N) return;
+  extern __shared__ __align__(16) unsigned char rt_smem[];
+  V4 *s_an = (V4 *)rt_smem;
+  V4 *s_rel = s_an + a.hf_cap;
+  int32_t *s_nbr = (int32_t *)(s_an + (MODE == 2 ? 3 : 1) * a.hf_cap);
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;  // whole padding workgroup
+  const int64_t c0 = lb * CPB;
+  const int64_t cell = c0 + threadIdx.x / LPC;
+  const bool live = cell < a.N;
   const int l = threadIdx.x % LPC;
   const int K = a.K;
-  rt_lane_angles<T, LPC, APL> ang;
+  int H0 = 0;
+  if (MODE != 0) {
+    const V4 *an = (const V4 *)a.hf_an;
+    const V4 *rel = (const V4 *)a.hf_rel;
+    const int64_t c1 = c0 + CPB < a.N ? c0 + CPB : a.N;
+    H0 = a.row_ptr[c0];
+    const int nH = a.row_ptr[c1] - H0;  // <= hf_cap by construction
+    for (int i = threadIdx.x; i < nH; i += RT_BLOCK) {
+      s_nbr[i] = a.hf_nbr[H0 + i];
+      s_an[i] = an[H0 + i];
+      if (MODE == 2) {
+        s_rel[2 * i] = rel[2 * (H0 + i)];
+        s_rel[2 * i + 1] = rel[2 * (H0 + i) + 1];
+      }
+    }
+    __syncthreads();
+  }
+  if (!live) return;
+  rt_lane_angles<T, LPC, APL, FULL> ang;
   ang.load(a.dirs, a.W, K, l);
 
   const T *Iin = (const T *)a.I_in;
@@ -45,19 +73,18 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
 #pragma unroll
     for (int q = 0; q < APL; ++q) acc[q] = (T)Vn * Ic[q];
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
-    const V4 *an = (const V4 *)a.hf_an;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
     if (MODE == 1) {
       for (int h = h0; h < h1; h += U) {
-        // batch metadata; slots past the cell's last face read face h0 with a zero record
+        // batch metadata; slots past the cell's last face reuse face h0 with a zero record
         int64_t j[U];
         V4 r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool v = h + u < h1;
-          const int hc = v ? h + u : h0;
-          j[u] = a.hf_nbr[hc];
-          r[u] = an[hc];
+          const int i = (v ? h + u : h0) - H0;
+          j[u] = s_nbr[i];
+          r[u] = s_an[i];
           if (!v) r[u] = V4{T(0), T(0), T(0), T(0)};
         }
         T x[U][APL];
@@ -80,7 +107,6 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
       // reconstructed face states of the half-step intensities (PLM stage 2)
       const T *Ih = (const T *)a.I_half;
       const T *G = (const T *)a.grad;
-      const V4 *rel = (const V4 *)a.hf_rel;
       T hs[APL], gsx[APL], gsy[APL], gsz[APL];
 #pragma unroll
       for (int q = 0; q < APL; ++q) {
@@ -97,11 +123,11 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           const bool v = h + u < h1;
-          const int hc = v ? h + u : h0;
-          j[u] = a.hf_nbr[hc];
-          r[u] = an[hc];
-          r0[u] = rel[2 * hc];
-          r1[u] = rel[2 * hc + 1];
+          const int i = (v ? h + u : h0) - H0;
+          j[u] = s_nbr[i];
+          r[u] = s_an[i];
+          r0[u] = s_rel[2 * i];
+          r1[u] = s_rel[2 * i + 1];
           if (!v) r[u] = V4{T(0), T(0), T(0), T(0)};
         }
         T xh[UP][APL], xg0[UP][APL], xg1[UP][APL], xg2[UP][APL];
@@ -143,30 +169,26 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     const double Eg = a.etot[cell];
     const double kP = a.kP[cell], kJ = a.kJ[cell], ks = a.ks[cell];
     const double c = a.c_light;
-    const double vx = m0 / rho, vy = m1 / rho, vz = m2 / rho;
+    const double irho = rt_rcp(rho);
+    const double vx = m0 * irho, vy = m1 * irho, vz = m2 * irho;
     const double gam = 1.0 / sqrt(1.0 - (vx * vx + vy * vy + vz * vz) / (c * c));
     const double y = a.dt * a.c_red * rho;
     const double chi = kJ + ks;
     const T tg = (T)gam, tvx = (T)(vx / c), tvy = (T)(vy / c), tvz = (T)(vz / c), tyc = (T)(y * chi);
-    double sE = 0, sFx = 0, sFy = 0, sFz = 0, sQ = 0, s1 = 0, sG = 0, sI = 0;
+    double sQ = 0, s1 = 0, sG = 0, sI = 0;
     // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
     // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S, so pass 2 keeps
-    // only Ir = I r and Br = r / Gamma^3.
-    T Br[APL];
+    // only I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).
+    T I0[APL], Br[APL];
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
-      const double Id = (double)Ic[q];
-      const double wq = ang.w[q];
-      sE += wq * Id;
-      sFx += wq * (double)ang.dx[q] * Id;
-      sFy += wq * (double)ang.dy[q] * Id;
-      sFz += wq * (double)ang.dz[q] * Id;
+      I0[q] = Ic[q];
       const T G = tg * (T(1) - (tvx * ang.dx[q] + tvy * ang.dy[q] + tvz * ang.dz[q]));
       const T iG = rt_rcp(G);
       const T iG2 = iG * iG;
       const T G2 = G * G;
       const T r = rt_rcp(T(1) + tyc * G);
-      const double qk = wq * (double)iG2;
+      const double qk = ang.w[q] * (double)iG2;
       sQ += qk;
       s1 += qk * (double)r;
       sG += qk * (double)(G * r);
@@ -174,50 +196,48 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
       Ic[q] *= r;
       Br[q] = r * iG2 * iG;
     }
-    sE = rt_group_sum<LPC>(sE);
-    sFx = rt_group_sum<LPC>(sFx);
-    sFy = rt_group_sum<LPC>(sFy);
-    sFz = rt_group_sum<LPC>(sFz);
     sQ = rt_group_sum<LPC>(sQ);
     s1 = rt_group_sum<LPC>(s1);
     sG = rt_group_sum<LPC>(sG);
     sI = rt_group_sum<LPC>(sI);
-    const double S1 = s1 / sQ, SG = sG / sQ, SI = sI / sQ;
+    const double iQ = rt_rcp(sQ);
+    const double S1 = s1 * iQ, SG = sG * iQ, SI = sI * iQ;
     const double Dd = S1 + y * kJ * SG;
-    const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / (rho * a.cv);
+    const double iD = rt_rcp(Dd);
+    const double rcv = rho * a.cv;
+    const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * irho) * rt_rcp(rcv);
     const double fourpi = 4.0 * RT_PI;
-    const double Aq = a.dt * c * rho * kP * a.a_rad * S1 / Dd;
-    const double Bq = rho * a.cv;
-    const double Cq = rho * a.cv * Tn + a.dt * c * rho * fourpi * kJ * SI / Dd;
-    const double Tnew = rt_quartic_root(Aq, Bq, Cq);
+    const double Aq = a.dt * c * rho * kP * a.a_rad * S1 * iD;
+    const double Cq = rcv * Tn + a.dt * c * rho * fourpi * kJ * SI * iD;
+    const double Tnew = rt_quartic_root_from(Aq, rcv, Cq, Tn);
     const double T4 = Tnew * Tnew * Tnew * Tnew;
     const double planck = a.a_rad * T4 / fourpi;
-    const double Jc = (SI + y * kP * SG * planck) / Dd;
+    const double Jc = (SI + y * kP * SG * planck) * iD;
     const T ySrc = (T)(y * (kP * planck + ks * Jc));
-    // ---- 3. per-angle implicit update, boost back; 4. moments of the stored values ------
-    double tE = 0, tFx = 0, tFy = 0, tFz = 0;
+    // ---- 3. per-angle implicit update, boost back; 4. radiation energy and momentum lost
+    //         by the stored values, handed to the gas (eqs. 35-36) ------------------------
+    double dE = 0, dFx = 0, dFy = 0, dFz = 0;
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
       const T out = Ic[q] + Br[q] * ySrc;
       Ic[q] = out;
-      const double od = (double)out;
-      const double wq = ang.w[q];
-      tE += wq * od;
-      tFx += wq * (double)ang.dx[q] * od;
-      tFy += wq * (double)ang.dy[q] * od;
-      tFz += wq * (double)ang.dz[q] * od;
+      const double wd = ang.w[q] * ((double)I0[q] - (double)out);
+      dE += wd;
+      dFx += wd * (double)ang.dx[q];
+      dFy += wd * (double)ang.dy[q];
+      dFz += wd * (double)ang.dz[q];
     }
-    tE = rt_group_sum<LPC>(tE);
-    tFx = rt_group_sum<LPC>(tFx);
-    tFy = rt_group_sum<LPC>(tFy);
-    tFz = rt_group_sum<LPC>(tFz);
+    dE = rt_group_sum<LPC>(dE);
+    dFx = rt_group_sum<LPC>(dFx);
+    dFy = rt_group_sum<LPC>(dFy);
+    dFz = rt_group_sum<LPC>(dFz);
     if (l == 0) {
       if (a.write_gas) {
-        a.etot[cell] = Eg + (c / a.c_red) * fourpi * (sE - tE);
+        a.etot[cell] = Eg + (c / a.c_red) * fourpi * dE;
         const double f = fourpi / a.c_red;
-        a.mom[3 * cell] = m0 + f * (sFx - tFx);
-        a.mom[3 * cell + 1] = m1 + f * (sFy - tFy);
-        a.mom[3 * cell + 2] = m2 + f * (sFz - tFz);
+        a.mom[3 * cell] = m0 + f * dFx;
+        a.mom[3 * cell + 1] = m1 + f * dFy;
+        a.mom[3 * cell + 2] = m2 + f * dFz;
       }
       if (a.T_out) a.T_out[cell] = Tnew;
     }
@@ -230,17 +250,25 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   if (MODE != 0 && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
 }
 
-template <typename T, int LPC, int APL> hipError_t launch(const rt_step_args &a, hipStream_t s) {
+template <typename T, int LPC, int APL, bool FULL> hipError_t launch_mode(const rt_step_args &a, hipStream_t s) {
+  using V4 = typename rt_vec4<T>::type;
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (a.N + cpb - 1) / cpb;
   const dim3 grid((unsigned)rt_grid_for(nblk)), block(RT_BLOCK);
+  const size_t per = (a.do_transport == 2 ? 3 : 1) * sizeof(V4) + sizeof(int32_t);
+  const size_t smem = a.do_transport ? per * (size_t)a.hf_cap : 0;
+  if (smem > 65536) return hipErrorInvalidConfiguration;  // more face records per workgroup than LDS holds
   switch (a.do_transport) {
-    case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0>), grid, block, 0, s, a, nblk); break;
-    case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1>), grid, block, 0, s, a, nblk); break;
-    case 2: hipLaunchKernelGGL((k_step<T, LPC, APL, 2>), grid, block, 0, s, a, nblk); break;
+    case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0, FULL>), grid, block, smem, s, a, nblk); break;
+    case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1, FULL>), grid, block, smem, s, a, nblk); break;
+    case 2: hipLaunchKernelGGL((k_step<T, LPC, APL, 2, FULL>), grid, block, smem, s, a, nblk); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T, int LPC, int APL> hipError_t launch(const rt_step_args &a, hipStream_t s) {
+  return a.K == LPC * APL ? launch_mode<T, LPC, APL, true>(a, s) : launch_mode<T, LPC, APL, false>(a, s);
 }
 
 template <typename T> hipError_t dispatch(const rt_step_args &a, hipStream_t s) {

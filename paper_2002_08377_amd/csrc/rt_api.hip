@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,8 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
   s.a_rad = p->a_rad;
   s.cv = p->cv;
   s.dt = p->dt;
+  // workgroups hold 16 cells when K is a multiple of 16 or above 64, else 32 (kernel dispatch)
+  s.hf_cap = (a->K % 16 == 0 || a->K > 64) ? m->hf_cap16 : m->hf_cap32;
   return s;
 }
 
@@ -237,6 +240,14 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
 
   rt_mesh *m = new rt_mesh;
   memset(m, 0, sizeof *m);
+  for (int64_t c = 0; c < N; c += 16) {
+    const int64_t e = c + 16 < N ? c + 16 : N;
+    m->hf_cap16 = std::max<int32_t>(m->hf_cap16, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
+  }
+  for (int64_t c = 0; c < N; c += 32) {
+    const int64_t e = c + 32 < N ? c + 32 : N;
+    m->hf_cap32 = std::max<int32_t>(m->hf_cap32, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
+  }
   (void)hipGetDevice(&m->device);
   m->N = N;
   m->F = F;

@@ -55,6 +55,23 @@ __device__ __forceinline__ double rt_quartic_root(double A, double B, double C) 
   return T;
 }
 
+// Same root, warm-started: a previous temperature Tw is used as the first iterate
+// when f(Tw) >= 0 (then it lies right of the root and the iterates still fall
+// monotonically); otherwise the start above.  Steps use the refined reciprocal.
+__device__ __forceinline__ double rt_rcp(double x);
+__device__ __forceinline__ double rt_quartic_root_from(double A, double B, double C, double Tw) {
+  if (!(A > 0.0)) return C / B;
+  double T = fmin(sqrt(sqrt(C / A)), C / B);
+  if (Tw > 0.0 && Tw < T && A * Tw * Tw * Tw * Tw + B * Tw - C >= 0.0) T = Tw;
+  for (int it = 0; it < 100; ++it) {
+    const double T3 = T * T * T;
+    const double Tn = T - (A * T3 * T + B * T - C) * rt_rcp(4.0 * A * T3 + B);
+    if (!(Tn < T)) break;
+    T = Tn;
+  }
+  return T;
+}
+
 // Reciprocals for per-angle arithmetic.  FP64: the hardware estimate refined by
 // two Newton steps (within an ulp of 1/x); FP32: the hardware estimate (1 ulp).
 __device__ __forceinline__ double rt_rcp(double x) {
@@ -66,8 +83,9 @@ __device__ __forceinline__ double rt_rcp(double x) {
 }
 __device__ __forceinline__ float rt_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// Angles of a lane: k = l + LPC * q for q < APL; ok[q] false past K.
-template <typename T, int LPC, int APL> struct rt_lane_angles {
+// Angles of a lane: k = l + LPC * q for q < APL; ok[q] false past K.  With FULL
+// (K == LPC * APL) every angle is live and k needs no clamping.
+template <typename T, int LPC, int APL, bool FULL = false> struct rt_lane_angles {
   T dx[APL], dy[APL], dz[APL];
   double w[APL];
   int k[APL];
@@ -76,9 +94,9 @@ template <typename T, int LPC, int APL> struct rt_lane_angles {
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
       const int kk = l + LPC * q;
-      ok[q] = kk < K;
-      k[q] = ok[q] ? kk : 0;
+      ok[q] = FULL || kk < K;
       // angles past K alias angle 0: loads stay in bounds, their weight is 0 and they are never stored
+      k[q] = ok[q] ? kk : 0;
       dx[q] = (T)dirs[3 * k[q]];
       dy[q] = (T)dirs[3 * k[q] + 1];
       dz[q] = (T)dirs[3 * k[q] + 2];

@@ -34,6 +34,8 @@ struct rt_mesh {
   void *lam_star;     // [N][k_max] doubles (RT_MESH_ADJOINT)
   double *red;        // reduction partials, RT_NDIAG * n_red_blocks doubles
   int64_t n_red_blocks;
+  int32_t hf_cap16;   // most half-faces of any 16 consecutive cells (workgroups of 16 cells)
+  int32_t hf_cap32;   // same for 32 consecutive cells
 };
 
 // ------------------------------------------------------------------------------------------
@@ -64,6 +66,7 @@ struct rt_step_args {
   const double *ks;
   double *T_out;
   double c_red, c_light, a_rad, cv, dt;
+  int hf_cap;        // half-faces of the largest workgroup range (LDS staging slots)
   int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2)
   int do_source;
   int write_gas;
