@@ -78,9 +78,16 @@ typedef struct {
   int32_t scheme; /* RT_UPWIND1 or RT_PLM_VL2 */
 } rt_params;
 
+/* Layout of an angle set (rt_angles.layout). */
+enum {
+  RT_ANGLES_GENERAL = 0,  /* no assumption */
+  RT_ANGLES_ANTIPODAL = 1 /* K even; dir[k + K/2] = -dir[k] and weight[k + K/2] = weight[k] for k < K/2 */
+};
+
 /* Discrete ordinates: K unit directions and weights summing to one (device memory). */
 typedef struct {
   int32_t K;            /* 1 <= K <= k_max of the mesh (and <= RT_K_MAX) */
+  int32_t layout;       /* RT_ANGLES_*; set it with rt_angles_layout(); a wrong claim gives wrong results */
   const double *dir;    /* device [K][3], unit vectors */
   const double *weight; /* device [K], sum = 1 */
 } rt_angles;
@@ -88,6 +95,16 @@ typedef struct {
 const char *rt_strerror(int code);
 const char *rt_last_error(void);
 int rt_version(void);
+
+/*
+ * Detect the layout of an angle set from HOST copies of its arrays: *layout is
+ * RT_ANGLES_ANTIPODAL when K is even and, exactly, dir[k + K/2] = -dir[k] and
+ * weight[k + K/2] = weight[k] for every k < K/2; else RT_ANGLES_GENERAL.  The
+ * antipodal layout lets the step kernel serve each pair of opposite angles with
+ * one dot product per face (the paper's direction sets are octant-symmetric).
+ * Errors: RT_EINVAL on NULL pointers or K outside [1, RT_K_MAX].
+ */
+int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t *layout);
 
 /*
  * Upload a periodic Voronoi mesh and prepare it for steps (section 2: cells,

@@ -59,6 +59,8 @@ int check_call(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
   if (a->K < 1 || a->K > m->k_max || a->K > RT_K_MAX)
     return fail(RT_EINVAL, "K=%d outside [1, k_max=%d]", a->K, m->k_max);
   if (!a->dir || !a->weight) return fail(RT_EINVAL, "angle arrays are NULL");
+  if (a->layout != RT_ANGLES_GENERAL && !(a->layout == RT_ANGLES_ANTIPODAL && a->K % 2 == 0))
+    return fail(RT_EINVAL, "invalid angle layout %d for K=%d", a->layout, a->K);
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(RT_EINVAL, "dt must be positive and finite");
   if (!(p->c_red > 0.0) || !isfinite(p->c_red)) return fail(RT_EINVAL, "c_red must be positive");
   if (!(p->c_light >= p->c_red) || !isfinite(p->c_light)) return fail(RT_EINVAL, "c_light must be >= c_red");
@@ -101,8 +103,14 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
   s.a_rad = p->a_rad;
   s.cv = p->cv;
   s.dt = p->dt;
-  // workgroups hold 16 cells when K is a multiple of 16 or above 64, else 32 (kernel dispatch)
-  s.hf_cap = (a->K % 16 == 0 || a->K > 64) ? m->hf_cap16 : m->hf_cap32;
+  s.inv_c = 1.0 / p->c_light;
+  s.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
+  s.m_gain = 4.0 * M_PI / p->c_red;
+  s.a_4pi = p->a_rad / (4.0 * M_PI);
+  s.paired = a->layout == RT_ANGLES_ANTIPODAL;
+  s.hf_cap16 = m->hf_cap16;
+  s.hf_cap32 = m->hf_cap32;
+  s.hf_cap64 = m->hf_cap64;
   return s;
 }
 
@@ -182,6 +190,21 @@ const char *rt_last_error(void) { return g_last_error.c_str(); }
 
 int rt_version(void) { return RTMM_VERSION; }
 
+int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t *layout) {
+  if (!dir || !weight || !layout) return fail(RT_EINVAL, "NULL argument");
+  if (K < 1 || K > RT_K_MAX) return fail(RT_EINVAL, "K=%d outside [1, %d]", K, RT_K_MAX);
+  *layout = RT_ANGLES_GENERAL;
+  if (K % 2) return RT_OK;
+  const int h = K / 2;
+  for (int k = 0; k < h; ++k) {
+    if (weight[k + h] != weight[k]) return RT_OK;
+    for (int c = 0; c < 3; ++c)
+      if (dir[3 * (k + h) + c] != -dir[3 * k + c]) return RT_OK;
+  }
+  *layout = RT_ANGLES_ANTIPODAL;
+  return RT_OK;
+}
+
 int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t flags, const double *gen,
                    const double *com, const double *vol, const double *mesh_vel, const int32_t *face_cells,
                    const int8_t *face_shift, const double *face_area, const double *face_normal,
@@ -247,6 +270,10 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   for (int64_t c = 0; c < N; c += 32) {
     const int64_t e = c + 32 < N ? c + 32 : N;
     m->hf_cap32 = std::max<int32_t>(m->hf_cap32, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
+  }
+  for (int64_t c = 0; c < N; c += 64) {
+    const int64_t e = c + 64 < N ? c + 64 : N;
+    m->hf_cap64 = std::max<int32_t>(m->hf_cap64, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
   }
   (void)hipGetDevice(&m->device);
   m->N = N;

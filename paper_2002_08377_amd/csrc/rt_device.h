@@ -55,14 +55,19 @@ __device__ __forceinline__ double rt_quartic_root(double A, double B, double C) 
   return T;
 }
 
-// Same root, warm-started: a previous temperature Tw is used as the first iterate
-// when f(Tw) >= 0 (then it lies right of the root and the iterates still fall
-// monotonically); otherwise the start above.  Steps use the refined reciprocal.
+// Same root, warm-started: a previous temperature Tw with f(Tw) >= 0 lies right of
+// the root, where the Newton iterates also fall monotonically, so it replaces the
+// cold start when it qualifies.  Steps use the refined reciprocal.
 __device__ __forceinline__ double rt_rcp(double x);
 __device__ __forceinline__ double rt_quartic_root_from(double A, double B, double C, double Tw) {
   if (!(A > 0.0)) return C / B;
-  double T = fmin(sqrt(sqrt(C / A)), C / B);
-  if (Tw > 0.0 && Tw < T && A * Tw * Tw * Tw * Tw + B * Tw - C >= 0.0) T = Tw;
+  double T;
+  if (Tw > 0.0 && A * Tw * Tw * Tw * Tw + B * Tw - C >= 0.0) {
+    T = Tw;
+  } else {
+    const double iA = rt_rcp(A), iB = rt_rcp(B);
+    T = fmin(sqrt(sqrt(C * iA)), C * iB);
+  }
   for (int it = 0; it < 100; ++it) {
     const double T3 = T * T * T;
     const double Tn = T - (A * T3 * T + B * T - C) * rt_rcp(4.0 * A * T3 + B);

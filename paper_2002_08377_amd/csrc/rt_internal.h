@@ -36,6 +36,7 @@ struct rt_mesh {
   int64_t n_red_blocks;
   int32_t hf_cap16;   // most half-faces of any 16 consecutive cells (workgroups of 16 cells)
   int32_t hf_cap32;   // same for 32 consecutive cells
+  int32_t hf_cap64;   // same for 64 consecutive cells
 };
 
 // ------------------------------------------------------------------------------------------
@@ -66,7 +67,13 @@ struct rt_step_args {
   const double *ks;
   double *T_out;
   double c_red, c_light, a_rad, cv, dt;
-  int hf_cap;        // half-faces of the largest workgroup range (LDS staging slots)
+  double inv_c;       // 1 / c
+  double e_gain;      // 4 pi c / cbar: gas energy per unit of sum W (I - I')
+  double m_gain;      // 4 pi / cbar: gas momentum per unit of sum W n (I - I')
+  double a_4pi;       // a / 4 pi
+  int paired;        // angles in the RT_ANGLES_ANTIPODAL layout
+  int hf_cap;        // LDS staging slots of the launched kernel (set at dispatch)
+  int hf_cap16, hf_cap32, hf_cap64;  // half-faces of the largest range of 16 / 32 / 64 cells
   int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2)
   int do_source;
   int write_gas;
@@ -79,6 +86,19 @@ hipError_t rt_launch_half_faces(rt_mesh *m, const int32_t *face_cells, const dou
                                 const double *face_normal, const double *face_centroid, const double *gen,
                                 const double *com, const int8_t *face_shift, hipStream_t s);
 hipError_t rt_launch_volume_rate(rt_mesh *m, hipStream_t s);
+
+// Lane layout of the step kernel for K angles: (lanes per cell << 8) | angles per lane.
+// Antipodal sets with K/2 a multiple of 8 (K/8 in 2..12) or of 4 (K/4 in {2, 6, 10}) use
+// the paired kernel; everything else 16 lanes (K a multiple of 16 or above 64) or 8.
+static inline int rt_step_lanes(int K, int paired) {
+  if (paired && K % 2 == 0) {
+    const int half = K / 2;
+    if (half % 8 == 0 && K / 8 >= 2 && K / 8 <= 12) return (8 << 8) | (K / 8);
+    if (half % 4 == 0 && (K / 4 == 2 || K / 4 == 6 || K / 4 == 10)) return (4 << 8) | (K / 4);
+  }
+  if (K % 16 == 0 || K > 64) return (16 << 8) | ((K + 15) / 16);
+  return (8 << 8) | ((K + 7) / 8);
+}
 
 hipError_t rt_launch_step(const rt_step_args &a, int dtype, hipStream_t s);
 hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, hipStream_t s);

@@ -171,7 +171,8 @@ def angle_set(K: int) -> tuple[np.ndarray, np.ndarray]:
     """Equal-weight, octant-symmetric unit vectors, K = 8*m(m+1)/2.
 
     First-octant points (mu_i, mu_j, mu_k) with i+j+k = m-1 and
-    mu_i^2 = mu_1^2 + i*(1 - 3 mu_1^2)/(m-1); all 8 sign flips; weights 1/K.
+    mu_i^2 = mu_1^2 + i*(1 - 3 mu_1^2)/(m-1); all 8 sign flips, ordered so that
+    direction k + K/2 is the antipode of direction k; weights 1/K.
     mu_1 is fixed by bisection so that the quadrature integrates n_x^4 exactly
     (mean 1/5), the classic level-symmetric choice.
     """
@@ -197,11 +198,10 @@ def angle_set(K: int) -> tuple[np.ndarray, np.ndarray]:
                 hi = mid
         mu1 = 0.5 * (lo + hi)
     oct_pts = _octant_points(m, mu1)
-    dirs = []
-    for sz in (1, -1):
-        for sy in (1, -1):
-            for sx in (1, -1):
-                dirs.append(oct_pts * np.array([sx, sy, sz]))
+    # octants with z > 0 first; the second half repeats them negated, so that
+    # direction k + K/2 is the antipode of direction k
+    upper = [(1, 1, 1), (-1, 1, 1), (1, -1, 1), (-1, -1, 1)]
+    dirs = [oct_pts * np.array(s) for s in upper] + [-oct_pts * np.array(s) for s in upper]
     d = np.concatenate(dirs, axis=0)
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     w = np.full(K, 1.0 / K)

@@ -40,7 +40,11 @@ class Params(ctypes.Structure):
 
 
 class _Angles(ctypes.Structure):
-    _fields_ = [("K", ctypes.c_int32), ("dir", ctypes.c_void_p), ("weight", ctypes.c_void_p)]
+    _fields_ = [("K", ctypes.c_int32), ("layout", ctypes.c_int32), ("dir", ctypes.c_void_p),
+                ("weight", ctypes.c_void_p)]
+
+
+ANGLES_GENERAL, ANGLES_ANTIPODAL = 0, 1
 
 
 _lib = None
@@ -58,6 +62,7 @@ _SIGS = {
     "rt_step_adjoint": [ctypes.c_void_p] * 17,
     "rt_flux_loss": [ctypes.c_void_p] * 8,
     "rt_diagnostics": [ctypes.c_void_p] * 9,
+    "rt_angles_layout": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
 }
 
 
@@ -119,14 +124,25 @@ def torch_dtype(dtype: int):
     return torch.float32 if dtype == F32 else torch.float64
 
 
-class AngleSet:
-    """Directions [K,3] and weights [K] resident on the device (float64)."""
+def angles_layout(dirs, weights) -> int:
+    """The library's classification of a host angle set (ANGLES_ANTIPODAL or ANGLES_GENERAL)."""
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    out = ctypes.c_int32(-1)
+    _check("rt_angles_layout", lib().rt_angles_layout(int(d.shape[0]), d.ctypes.data_as(ctypes.c_void_p),
+                                                     w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)))
+    return out.value
 
-    def __init__(self, dirs, weights, device="cuda"):
+
+class AngleSet:
+    """Directions [K,3] and weights [K] resident on the device (float64), with their layout."""
+
+    def __init__(self, dirs, weights, device="cuda", layout=None):
+        self.layout = angles_layout(dirs, weights) if layout is None else int(layout)
         self.dirs = torch.as_tensor(np.ascontiguousarray(dirs, dtype=np.float64), device=device)
         self.weights = torch.as_tensor(np.ascontiguousarray(weights, dtype=np.float64), device=device)
         self.K = int(self.dirs.shape[0])
-        self.c = _Angles(self.K, self.dirs.data_ptr(), self.weights.data_ptr())
+        self.c = _Angles(self.K, self.layout, self.dirs.data_ptr(), self.weights.data_ptr())
 
 
 class Mesh:

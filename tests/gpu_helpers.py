@@ -19,14 +19,14 @@ def rel_err(a, b):
 class DeviceProblem:
     """A seeded problem uploaded to the library, plus its oracle twin."""
 
-    def __init__(self, prob: inp.Problem, dtype=rt.F64, scheme=rt.UPWIND1, flags=0):
+    def __init__(self, prob: inp.Problem, dtype=rt.F64, scheme=rt.UPWIND1, flags=0, layout=None):
         self.p = prob
         st = prob.state
         self.dtype = dtype
         self.scheme = scheme
         self.mesh = rt.Mesh.from_inputs(prob.mesh, st.mesh_vel, k_max=prob.dirs.shape[0],
                                         flags=flags | (rt.MESH_PLM if scheme == rt.PLM_VL2 else 0))
-        self.angles = rt.AngleSet(prob.dirs, prob.weights)
+        self.angles = rt.AngleSet(prob.dirs, prob.weights, layout=layout)
         ph = prob.phys
         self.params = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, prob.dt, dtype, scheme)
         d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")

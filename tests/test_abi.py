@@ -68,4 +68,20 @@ def test_params_layout_matches_header():
     # c_red, c_light, a_rad, cv, dt (5 doubles) then dtype, scheme (2 int32)
     assert ctypes.sizeof(rt.Params) == 48
     assert rt.Params.dtype.offset == 40 and rt.Params.scheme.offset == 44
-    assert ctypes.sizeof(rt._Angles) == 24 and rt._Angles.dir.offset == 8
+    assert ctypes.sizeof(rt._Angles) == 24 and rt._Angles.layout.offset == 4 and rt._Angles.dir.offset == 8
+
+
+def test_angle_layout_detection():
+    from paper_2002_08377_amd import inputs as inp
+    for K in (8, 24, 48, 80):
+        d, w = inp.angle_set(K)
+        assert rt.angles_layout(d, w) == rt.ANGLES_ANTIPODAL
+        # any perturbation or reordering breaks the exact antipodal layout
+        d2 = d.copy(); d2[K - 1] = -d2[0]
+        assert rt.angles_layout(d2, w) == rt.ANGLES_GENERAL
+        w2 = w.copy(); w2[0] *= 1.0 + 1e-15
+        assert rt.angles_layout(d, w2) == rt.ANGLES_GENERAL
+        assert rt.angles_layout(d[:-1], w[:-1]) == rt.ANGLES_GENERAL
+    L = rt.lib()
+    out = ctypes.c_int32()
+    assert L.rt_angles_layout(0, None, None, ctypes.byref(out)) == rt.RT_EINVAL

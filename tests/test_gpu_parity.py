@@ -44,11 +44,13 @@ def test_mesh_geometry_matches_oracle():
     assert info["n_half_faces"] == 2 * p.mesh.n_faces
 
 
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 @pytest.mark.parametrize("K", [8, 20, 24, 48, 80])
-def test_transport_matches_oracle(dtype, K):
+def test_transport_matches_oracle(dtype, K, layout):
+    """layout None: detected (antipodal sets take the paired kernel); GENERAL: forced general kernel."""
     p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
-    dp = DeviceProblem(p, dtype=dtype)
+    dp = DeviceProblem(p, dtype=dtype, layout=layout)
     st = p.state
     rt.transport_step(dp.mesh, dp.params, dp.angles, dp.I, dp.I2, dp.vol)
     Io, vo = orc.transport_upwind(dp.om, p.dirs, p.phys.c_red, p.dt, st.I, st.vol)
@@ -57,11 +59,12 @@ def test_transport_matches_oracle(dtype, K):
     assert rel_err(dp.vol.cpu().numpy(), vo) < 1e-15
 
 
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-@pytest.mark.parametrize("K", [8, 20, 48, 80])
-def test_source_matches_oracle(dtype, K):
+@pytest.mark.parametrize("K", [8, 20, 24, 48, 80])
+def test_source_matches_oracle(dtype, K, layout):
     p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
-    dp = DeviceProblem(p, dtype=dtype)
+    dp = DeviceProblem(p, dtype=dtype, layout=layout)
     st = p.state
     # stiffen half the cells
     kap = st.kP.copy()
@@ -78,11 +81,12 @@ def test_source_matches_oracle(dtype, K):
     assert rel_err(dp.mom.cpu().numpy(), mo) < max(tol_gas, 1e-12)
 
 
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_forward_12c_24a_10steps(dtype):
+def test_forward_12c_24a_10steps(dtype, layout):
     """The plain forward workload at its full size: 12^3 cells, 24 angles, 10 steps."""
     p = inp.make_problem(0)
-    dp = DeviceProblem(p, dtype=dtype)
+    dp = DeviceProblem(p, dtype=dtype, layout=layout)
     dp.run_gpu(p.steps)
     so, To = dp.run_oracle(p.steps)
     assert rel_err(dp.host(dp.I), so.I) < TOL[dtype]
@@ -125,9 +129,10 @@ def test_gradient_matches_oracle(dtype):
     assert rel_err(dp.host(g), go) < (1e-11 if dtype == rt.F64 else 1e-4)
 
 
+@pytest.mark.parametrize("K", [24, 48])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_plm_steps_match_oracle(dtype):
-    p = _prob(1, n=9, K=24, steps=4)
+def test_plm_steps_match_oracle(dtype, K):
+    p = _prob(1, n=9, K=K, steps=4)
     dp = DeviceProblem(p, dtype=dtype, scheme=rt.PLM_VL2)
     dp.run_gpu(4)
     so, To = dp.run_oracle(4, "plm_vl2")
