@@ -3,7 +3,7 @@
 // angles.  One pass reads the cell's intensity row, gathers the neighbour rows of
 // its faces through the half-face index (no atomics), updates the charges, runs the
 // source on the transported row while it is in registers, and writes the row once.
-#include "rt_device.h"
+#include "rt_step_common.h"
 
 namespace {
 
@@ -11,42 +11,6 @@ namespace {
 // used, so one memory round trip serves U faces.
 template <typename T> struct rt_batch { static constexpr int U = 4; };
 template <> struct rt_batch<double> { static constexpr int U = 2; };
-
-// Angles held by one lane.
-//  General layout: k_q = l + LPC q for q < APL; past K (only when !FULL) the slot
-//    aliases angle 0 with weight 0 and is never stored.
-//  Paired layout (angle k + K/2 is the antipode of angle k and has its weight; needs
-//    K = LPC APL): the lane holds P = APL/2 angles k_q = l + LPC q and their
-//    antipodes k_q + K/2 in slots q + P, so one stored direction serves both and
-//    one dot product per face serves both fluxes.
-template <typename T, int LPC, int APL, bool FULL, bool PAIRED> struct rt_step_angles {
-  static constexpr int P = PAIRED ? APL / 2 : APL;
-  T x[P], y[P], z[P];
-  double w[P];
-  int k[APL];
-  bool ok[APL];
-  __device__ __forceinline__ void load(const double *dirs, const double *W, int K, int l) {
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const int kk = l + LPC * q;
-      ok[q] = FULL || PAIRED || kk < K;
-      k[q] = ok[q] ? kk : 0;
-      x[q] = (T)dirs[3 * k[q]];
-      y[q] = (T)dirs[3 * k[q] + 1];
-      z[q] = (T)dirs[3 * k[q] + 2];
-      w[q] = ok[q] ? W[k[q]] : 0.0;
-      if (PAIRED) {
-        k[q + P] = k[q] + K / 2;
-        ok[q + P] = true;
-      }
-    }
-  }
-  // direction and weight of slot q (q is a compile-time constant after unrolling)
-  __device__ __forceinline__ T dx(int q) const { return PAIRED && q >= P ? -x[q - P] : x[q]; }
-  __device__ __forceinline__ T dy(int q) const { return PAIRED && q >= P ? -y[q - P] : y[q]; }
-  __device__ __forceinline__ T dz(int q) const { return PAIRED && q >= P ? -z[q - P] : z[q]; }
-  __device__ __forceinline__ double wt(int q) const { return PAIRED && q >= P ? w[q - P] : w[q]; }
-};
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
 // transport of PLM stage 2 (+ source).  Separate instantiations keep each one's
@@ -203,98 +167,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     for (int q = 0; q < APL; ++q) Ic[q] = acc[q] * inv;
   }
 
-  if (a.do_source) {
-    // ---- implicit source (section 2.3): 1-2. comoving sums and the temperature ----------
-    const double rho = a.rho[cell];
-    const double m0 = a.mom[3 * cell], m1 = a.mom[3 * cell + 1], m2 = a.mom[3 * cell + 2];
-    const double Eg = a.etot[cell];
-    const double kP = a.kP[cell], kJ = a.kJ[cell], ks = a.ks[cell];
-    const double c = a.c_light;
-    const double irho = rt_rcp(rho);
-    const double vx = m0 * irho, vy = m1 * irho, vz = m2 * irho;
-    const double ic = a.inv_c;
-    const double gam = rsqrt(1.0 - (vx * vx + vy * vy + vz * vz) * (ic * ic));
-    const double y = a.dt * a.c_red * rho;
-    const double chi = kJ + ks;
-    const T tg = (T)gam, tvx = (T)(vx * ic), tvy = (T)(vy * ic), tvz = (T)(vz * ic), tyc = (T)(y * chi);
-    double sQ = 0, s1 = 0, sG = 0, sI = 0;
-    // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
-    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S, so pass 2 keeps
-    // only I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).
-    T I0[APL], Br[APL];
-    auto pass1 = [&](int q, T G) {
-      I0[q] = Ic[q];
-      const T iG = rt_rcp(G);
-      const T iG2 = iG * iG;
-      const T G2 = G * G;
-      const T r = rt_rcp(T(1) + tyc * G);
-      const double qk = ang.wt(q) * (double)iG2;
-      sQ += qk;
-      s1 += qk * (double)r;
-      sG += qk * (double)(G * r);
-      sI += qk * (double)(G2 * G2 * Ic[q] * r);
-      Ic[q] *= r;
-      Br[q] = r * iG2 * iG;
-    };
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      // Gamma = gamma (1 - v.n/c); the antipode has gamma (1 + v.n/c)
-      const T vn = tvx * ang.x[q] + tvy * ang.y[q] + tvz * ang.z[q];
-      pass1(q, tg * (T(1) - vn));
-      if (PAIRED) pass1(q + P, tg * (T(1) + vn));
-    }
-    sQ = rt_group_sum<LPC>(sQ);
-    s1 = rt_group_sum<LPC>(s1);
-    sG = rt_group_sum<LPC>(sG);
-    sI = rt_group_sum<LPC>(sI);
-    const double iQ = rt_rcp(sQ);
-    const double S1 = s1 * iQ, SG = sG * iQ, SI = sI * iQ;
-    const double Dd = S1 + y * kJ * SG;
-    const double iD = rt_rcp(Dd);
-    const double rcv = rho * a.cv;
-    const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * irho) * rt_rcp(rcv);
-    const double fourpi = 4.0 * RT_PI;
-    const double Aq = a.dt * c * rho * kP * a.a_rad * S1 * iD;
-    const double Cq = rcv * Tn + a.dt * c * rho * fourpi * kJ * SI * iD;
-    const double Tnew = rt_quartic_root_from(Aq, rcv, Cq, Tn);
-    const double T4 = Tnew * Tnew * Tnew * Tnew;
-    const double planck = a.a_4pi * T4;
-    const double Jc = (SI + y * kP * SG * planck) * iD;
-    const T ySrc = (T)(y * (kP * planck + ks * Jc));
-    // ---- 3. per-angle implicit update, boost back; 4. radiation energy and momentum lost
-    //         by the stored values, handed to the gas (eqs. 35-36) ------------------------
-    double dE = 0, dFx = 0, dFy = 0, dFz = 0;
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const T out = Ic[q] + Br[q] * ySrc;
-      Ic[q] = out;
-      double wd = ang.w[q] * ((double)I0[q] - (double)out);
-      dE += wd;
-      if (PAIRED) {
-        const T out2 = Ic[q + P] + Br[q + P] * ySrc;
-        Ic[q + P] = out2;
-        const double wd2 = ang.w[q] * ((double)I0[q + P] - (double)out2);
-        dE += wd2;
-        wd -= wd2;  // the antipode's direction is -n
-      }
-      dFx += wd * (double)ang.x[q];
-      dFy += wd * (double)ang.y[q];
-      dFz += wd * (double)ang.z[q];
-    }
-    dE = rt_group_sum<LPC>(dE);
-    dFx = rt_group_sum<LPC>(dFx);
-    dFy = rt_group_sum<LPC>(dFy);
-    dFz = rt_group_sum<LPC>(dFz);
-    if (l == 0) {
-      if (a.write_gas) {
-        a.etot[cell] = Eg + a.e_gain * dE;
-        a.mom[3 * cell] = m0 + a.m_gain * dFx;
-        a.mom[3 * cell + 1] = m1 + a.m_gain * dFy;
-        a.mom[3 * cell + 2] = m2 + a.m_gain * dFz;
-      }
-      if (a.T_out) a.T_out[cell] = Tnew;
-    }
-  }
+  if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
 
   T *Iout = (T *)a.I_out;
 #pragma unroll

@@ -265,3 +265,24 @@ def test_error_paths():
     with pytest.raises(rt.RTError) as e:
         rt.diagnostics(dp.mesh, dp.params, dp.angles, dp.I, dp.vol, dp.etot, dp.mom)
     assert e.value.code == rt.RT_ENONFINITE
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_eight_byte_aligned_arrays(dtype):
+    """The ABI asks only 8-byte alignment: arrays offset from a 16-byte boundary give the same result."""
+    p = _prob(0, n=8, K=80)
+    dp = DeviceProblem(p, dtype=dtype)
+    N, K = p.state.I.shape
+    td = rt.torch_dtype(dtype)
+    off = 16 // torch.tensor([], dtype=td).element_size() // 2  # half a 16-byte vector
+    buf_in = torch.zeros(N * K + off, dtype=td, device="cuda")
+    buf_out = torch.zeros(N * K + off, dtype=td, device="cuda")
+    I_u = buf_in[off:].view(N, K)
+    I_u.copy_(dp.I)
+    O_u = buf_out[off:].view(N, K)
+    vol2 = dp.vol.clone()
+    rt.transport_step(dp.mesh, dp.params, dp.angles, dp.I, dp.I2, dp.vol)
+    rt.transport_step(dp.mesh, dp.params, dp.angles, I_u, O_u, vol2)
+    torch.cuda.synchronize()
+    assert I_u.data_ptr() % 16 != 0
+    assert rel_err(dp.host(O_u), dp.host(dp.I2)) < (1e-14 if dtype == rt.F64 else 1e-6)
