@@ -123,6 +123,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override cells per side (default 128)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--forms", default="f32,f64", help="precision forms to run (f32, f64)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy an FP32 intensity-sized array 3 times (a kernel of known traffic, "
+                         "to scale hardware byte counters)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
@@ -143,9 +147,24 @@ def main():
     mesh = rt.Mesh.from_inputs(prob.mesh, prob.state.mesh_vel, k_max=K)
     angles = rt.AngleSet(prob.dirs, prob.weights)
 
+    if args.copy_calibration:
+        x = torch.ones(N * K, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {N * K * 4} bytes")
+        del x, y
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
     for name, code in (("f32", rt.F32), ("f64", rt.F64)):
-        res[name] = run_form(prob, mesh, angles, code, args.steps, args.warmup, log)
+        if name in forms:
+            res[name] = run_form(prob, mesh, angles, code, args.steps, args.warmup, log)
+    if not ("f32" in res and "f64" in res):
+        mesh.free()
+        print(json.dumps({name: {"ms_per_step": r["wall"] * 1e3 / args.steps, "kernel_ms": r["kernel_ms"]}
+                          for name, r in res.items()}), flush=True)
+        return
 
     ca = N * K * args.steps
     err = float(np.max(np.abs(res["f32"]["I"] - res["f64"]["I"])) / np.max(np.abs(res["f64"]["I"])))

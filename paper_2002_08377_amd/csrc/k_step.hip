@@ -33,8 +33,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   const int64_t lb = rt_logical_block(nblk);
   if (lb < 0) return;  // whole padding workgroup
   const int64_t c0 = lb * CPB;
-  const int64_t cell = c0 + threadIdx.x / LPC;
-  const bool live = cell < a.N;
+  const int g = threadIdx.x / LPC;
+  const bool live = c0 + g < a.N;
+  const int64_t cell = live ? c0 + a.wg_order[c0 + g] : c0;
   const int l = threadIdx.x % LPC;
   const int K = a.K;
   int H0 = 0;
@@ -184,6 +185,7 @@ hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
   using V4 = typename rt_vec4<T>::type;
   rt_step_args a = args;
   a.hf_cap = LPC == 16 ? a.hf_cap16 : LPC == 8 ? a.hf_cap32 : a.hf_cap64;
+  a.wg_order = LPC == 16 ? a.wg_order16 : LPC == 8 ? a.wg_order32 : a.wg_order64;
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (a.N + cpb - 1) / cpb;
   const dim3 grid((unsigned)rt_grid_for(nblk)), block(RT_BLOCK);

@@ -45,7 +45,7 @@ template <typename P> hipError_t dmalloc(P **p, size_t bytes) {
 void free_mesh_arrays(rt_mesh *m) {
   void *ptrs[] = {m->vol0,    m->D,       m->wn,       m->row_ptr, m->hf_nbr, m->hf_face, m->hf_an64,
                   m->hf_an32, m->hf_gp64, m->hf_rel64, m->hf_gp32, m->hf_rel32, m->I_half, m->grad,
-                  m->lam_star, m->red};
+                  m->lam_star, m->red, m->wg_order16, m->wg_order32, m->wg_order64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -111,6 +111,9 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
   s.hf_cap16 = m->hf_cap16;
   s.hf_cap32 = m->hf_cap32;
   s.hf_cap64 = m->hf_cap64;
+  s.wg_order16 = m->wg_order16;
+  s.wg_order32 = m->wg_order32;
+  s.wg_order64 = m->wg_order64;
   return s;
 }
 
@@ -275,6 +278,25 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
     const int64_t e = c + 64 < N ? c + 64 : N;
     m->hf_cap64 = std::max<int32_t>(m->hf_cap64, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
   }
+  // within every workgroup of 16 / 32 / 64 consecutive cells, order the cells by face count
+  std::vector<uint8_t> order16((size_t)N), order32((size_t)N), order64((size_t)N);
+  {
+    std::vector<int> idx;
+    auto fill_order = [&](int cpb, std::vector<uint8_t> &ord) {
+      for (int64_t c = 0; c < N; c += cpb) {
+        const int n = (int)std::min<int64_t>(cpb, N - c);
+        idx.resize((size_t)n);
+        for (int g = 0; g < n; ++g) idx[(size_t)g] = g;
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+          return cnt[(size_t)(c + x) + 1] < cnt[(size_t)(c + y) + 1];
+        });
+        for (int g = 0; g < n; ++g) ord[(size_t)(c + g)] = (uint8_t)idx[(size_t)g];
+      }
+    };
+    fill_order(16, order16);
+    fill_order(32, order32);
+    fill_order(64, order64);
+  }
   (void)hipGetDevice(&m->device);
   m->N = N;
   m->F = F;
@@ -309,6 +331,9 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   }
   if (flags & RT_MESH_ADJOINT) RT_ALLOC(m->lam_star, sizeof(double) * N * k_max);
   RT_ALLOC(m->red, sizeof(double) * RT_NDIAG * nred);
+  RT_ALLOC(m->wg_order16, N);
+  RT_ALLOC(m->wg_order32, N);
+  RT_ALLOC(m->wg_order64, N);
   // temporaries of the upload
   double *d_gen = nullptr, *d_com = nullptr, *d_w = nullptr, *d_area = nullptr, *d_nrm = nullptr, *d_cen = nullptr;
   int32_t *d_fc = nullptr;
@@ -339,6 +364,9 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   H2D(m->vol0, vol, sizeof(double) * N);
   H2D(m->row_ptr, row_ptr.data(), sizeof(int32_t) * (N + 1));
   H2D(m->hf_face, hf_face.data(), sizeof(int32_t) * H);
+  H2D(m->wg_order16, order16.data(), N);
+  H2D(m->wg_order32, order32.data(), N);
+  H2D(m->wg_order64, order64.data(), N);
   H2D(d_gen, gen, sizeof(double) * 3 * N);
   H2D(d_com, com, sizeof(double) * 3 * N);
   H2D(d_w, mesh_vel, sizeof(double) * 3 * N);

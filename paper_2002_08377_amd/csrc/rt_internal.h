@@ -37,6 +37,10 @@ struct rt_mesh {
   int32_t hf_cap16;   // most half-faces of any 16 consecutive cells (workgroups of 16 cells)
   int32_t hf_cap32;   // same for 32 consecutive cells
   int32_t hf_cap64;   // same for 64 consecutive cells
+  // per workgroup of 16 / 32 / 64 consecutive cells, the cells ordered by face count:
+  // lane group g of the workgroup starting at cell c0 takes cell c0 + wg_order*[c0 + g], so
+  // each wave holds cells of similar face counts and its face loop pads less
+  uint8_t *wg_order16, *wg_order32, *wg_order64;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -74,6 +78,8 @@ struct rt_step_args {
   int paired;        // angles in the RT_ANGLES_ANTIPODAL layout
   int hf_cap;        // LDS staging slots of the launched kernel (set at dispatch)
   int hf_cap16, hf_cap32, hf_cap64;  // half-faces of the largest range of 16 / 32 / 64 cells
+  const uint8_t *wg_order16, *wg_order32, *wg_order64;  // cell order within workgroups
+  const uint8_t *wg_order;                              // the one of the launched kernel
   int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2)
   int do_source;
   int write_gas;
