@@ -1,0 +1,143 @@
+"""Differentiable radiation steps: a torch.autograd.Function over the C ABI.
+
+The forward pass advances S first-order steps (transport then implicit source,
+sections 2.2-2.3) with the fused step call and keeps a checkpoint of the state
+(I, E_g, rho v, V) at the start of every segment of `ckpt_every` steps.  The
+backward pass walks the segments in reverse: it restores the segment's
+checkpoint, re-runs its steps with the split transport / source calls, which
+give the same values bit for bit as the fused call, while recording what the
+adjoint of each step needs (the transported intensities I* and the
+start-of-step volume and gas state), and then applies the per-step adjoint in
+reverse order.  Peak memory is therefore one checkpoint per segment plus
+`ckpt_every` recorded steps, instead of all S steps.
+
+The opacities are tied, kappa_P = kappa_J = kappa_a, so dL/dkappa_a is the sum
+of the two partial derivatives; the library increments both into one buffer.
+Every step of the computation runs in the library's kernels; this module only
+allocates buffers and orders calls on the current stream.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import rt
+
+
+@dataclass
+class RTSystem:
+    """Everything of the problem except the differentiable inputs: the uploaded mesh
+    (with RT_MESH_ADJOINT scratch), the step parameters (first-order scheme), the
+    angle set, and the per-cell density, scattering opacity and initial volumes."""
+
+    mesh: rt.Mesh
+    params: rt.Params
+    angles: rt.AngleSet
+    rho: torch.Tensor
+    ks: torch.Tensor
+    vol0: torch.Tensor
+
+    def check(self):
+        if self.params.scheme != rt.UPWIND1:
+            raise ValueError("the adjoint covers the first-order upwind scheme only")
+        if not (self.mesh.flags & rt.MESH_ADJOINT):
+            raise ValueError("the mesh must be uploaded with MESH_ADJOINT")
+
+
+class RTSteps(torch.autograd.Function):
+    """(I^0, kappa_a, E_g^0, (rho v)^0) -> (I^S, E_g^S, (rho v)^S) after n_steps steps.
+
+    Gradients flow to all four tensor inputs.  ckpt_every >= 1 sets the segment
+    length of the recompute (the last segment may be shorter)."""
+
+    @staticmethod
+    def forward(ctx, I0, kappa_a, etot0, mom0, system: RTSystem, n_steps: int, ckpt_every: int):
+        system.check()
+        if n_steps < 0 or ckpt_every < 1:
+            raise ValueError("n_steps >= 0 and ckpt_every >= 1 required")
+        td = rt.torch_dtype(system.params.dtype)
+        I = I0.detach().to(td).contiguous().clone()
+        I2 = torch.empty_like(I)
+        kap = kappa_a.detach().contiguous()
+        etot = etot0.detach().contiguous().clone()
+        mom = mom0.detach().contiguous().clone()
+        vol = system.vol0.detach().contiguous().clone()
+        ckpts = []
+        for n in range(n_steps):
+            if n % ckpt_every == 0:
+                ckpts.append((I.clone(), etot.clone(), mom.clone(), vol.clone()))
+            rt.step(system.mesh, system.params, system.angles, I, I2, vol, system.rho, mom, etot, kap, kap,
+                    system.ks)
+            I, I2 = I2, I
+        ctx.system = system
+        ctx.n_steps = n_steps
+        ctx.ckpt_every = ckpt_every
+        ctx.ckpts = ckpts
+        ctx.save_for_backward(kap)
+        ctx.in_dtype = I0.dtype
+        return I, etot, mom
+
+    @staticmethod
+    def backward(ctx, gI, gE, gM):
+        (kap,) = ctx.saved_tensors
+        s = ctx.system
+        td = rt.torch_dtype(s.params.dtype)
+        N, K = s.mesh.n_cells, s.angles.K
+        dev = kap.device
+        lamI = (gI.to(td).contiguous().clone() if gI is not None
+                else torch.zeros((N, K), dtype=td, device=dev))
+        lamE = (gE.to(torch.float64).contiguous().clone() if gE is not None
+                else torch.zeros(N, dtype=torch.float64, device=dev))
+        lamM = (gM.to(torch.float64).contiguous().clone() if gM is not None
+                else torch.zeros((N, 3), dtype=torch.float64, device=dev))
+        dk = torch.zeros(N, dtype=torch.float64, device=dev)
+        L = ctx.ckpt_every
+        tape_I = [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps))]
+        for seg in reversed(range(len(ctx.ckpts))):
+            I, etot, mom, vol = (t.clone() for t in ctx.ckpts[seg])
+            n0 = seg * L
+            nseg = min(L, ctx.n_steps - n0)
+            tape = []
+            for n in range(nseg):
+                vol_n, mom_n, etot_n = vol.clone(), mom.clone(), etot.clone()
+                rt.transport_step(s.mesh, s.params, s.angles, I, tape_I[n], vol)
+                I.copy_(tape_I[n])
+                rt.source_implicit(s.mesh, s.params, s.angles, I, s.rho, mom, etot, kap, kap, s.ks)
+                tape.append((tape_I[n], vol_n, mom_n, etot_n))
+            for I_star, vol_n, mom_n, etot_n in reversed(tape):
+                rt.step_adjoint(s.mesh, s.params, s.angles, I_star, vol_n, s.rho, mom_n, etot_n, kap, kap, s.ks,
+                                lamI, lamE, lamM, dk, dk)
+        ctx.ckpts = None
+        return lamI.to(ctx.in_dtype), dk, lamE, lamM, None, None, None
+
+
+class FluxLoss(torch.autograd.Function):
+    """The weighted emergent-flux loss of the library (rt_flux_loss) as a scalar
+    tensor; its gradient with respect to I comes from the same call's seed output."""
+
+    @staticmethod
+    def forward(ctx, I, face_weight, system: RTSystem):
+        loss = torch.zeros(1, dtype=torch.float64, device=I.device)
+        Ic = I.detach().contiguous()
+        rt.flux_loss(system.mesh, system.params, system.angles, Ic, face_weight, loss)
+        ctx.system = system
+        ctx.face_weight = face_weight
+        ctx.shape, ctx.dtype, ctx.device = Ic.shape, Ic.dtype, Ic.device
+        ctx.Ic = Ic
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        seed = torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
+        rt.flux_loss(ctx.system.mesh, ctx.system.params, ctx.system.angles, ctx.Ic, ctx.face_weight,
+                     torch.zeros(1, dtype=torch.float64, device=ctx.device), seed)
+        return seed * g.to(ctx.dtype), None, None
+
+
+def rt_steps(I0, kappa_a, etot0, mom0, system: RTSystem, n_steps: int, ckpt_every: int = 8):
+    return RTSteps.apply(I0, kappa_a, etot0, mom0, system, n_steps, ckpt_every)
+
+
+def flux_loss(I, face_weight, system: RTSystem):
+    return FluxLoss.apply(I, face_weight, system)

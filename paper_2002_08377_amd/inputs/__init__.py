@@ -350,3 +350,12 @@ def loss_face_weights(mesh: Mesh, rng: np.random.Generator, x0: float = 0.5) -> 
     u = np.zeros(mesh.n_faces)
     u[ids] = sign * omega
     return u
+
+
+def fd_cells(mesh: Mesh, rng: np.random.Generator, count: int = 16, hops: float = 4.0,
+             x0: float = 0.5) -> np.ndarray:
+    """`count` distinct cells whose generators lie within `hops` lattice spacings of the
+    loss plane x = x0 (inside the domain of dependence of a few first-order steps),
+    drawn without replacement; used for finite-difference checks of gradients."""
+    near = np.nonzero(np.abs(mesh.gen[:, 0] - x0) < hops * mesh.h)[0]
+    return np.sort(rng.choice(near, size=min(count, near.size), replace=False))

@@ -1,0 +1,198 @@
+"""Differentiable radiation steps with checkpoint / recompute, through the C ABI.
+
+* The recompute of the backward pass uses the split transport / source calls
+  while the forward pass uses the fused step: the two must agree bit for bit,
+  in both precision forms and in the paired and general lane layouts.
+* The gradient of the emergent-flux loss through `RTSteps` (FP64) matches the
+  oracle's hand-written reverse mode to 1e-10 (normwise) and the loss to 1e-12.
+* The checkpoint interval changes memory, never values: gradients are equal bit
+  for bit for every interval, including ones that do not divide the step count.
+* Gradients with respect to all four inputs (I^0, kappa_a, E_g^0, (rho v)^0)
+  agree with central differences of the GPU forward along random directions.
+* At the adjoint workload's full size (32^3 cells, 48 angles, 20 steps) the
+  gradient at the 16 seeded cells near the loss plane matches central finite
+  differences to 1e-6 relative, plus the rounding floor of a difference quotient,
+  64 eps S / (2 e), where S is the summed magnitude of the loss's terms (the loss,
+  -0.026 here, is a small difference of face fluxes summing to ~115 in magnitude,
+  so a relative step of 1e-6 would sit below that floor).  Steps: 1e-4 relative
+  for kappa_a, 1e-3 for the intensity (the loss is nearly linear in it).
+* At the checkpointed workload's full size (96^3 cells, 80 angles, 40 steps,
+  checkpoints every 8) the FP32-transport gradient is compared with the FP64 one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from gpu_helpers import rel_err
+from paper_2002_08377_amd import inputs as inp
+from paper_2002_08377_amd import rt
+from paper_2002_08377_amd.autograd import RTSystem, flux_loss, rt_steps
+
+pytestmark = pytest.mark.gpu
+
+
+def _d(a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _system(p, dtype=rt.F64, layout=None):
+    st = p.state
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=p.dirs.shape[0], flags=rt.MESH_ADJOINT)
+    ph = p.phys
+    prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, dtype)
+    system = RTSystem(mesh, prm, rt.AngleSet(p.dirs, p.weights, layout=layout), _d(st.rho), _d(st.ks), _d(st.vol))
+    return system, dict(I0=_d(st.I), kap=_d(st.kP), etot=_d(st.etot), mom=_d(st.mom))
+
+
+def _grads(system, x, fw, steps, ckpt, gas_w=None):
+    I0, kap, etot, mom = (x[k].clone().requires_grad_() for k in ("I0", "kap", "etot", "mom"))
+    IS, ES, MS = rt_steps(I0, kap, etot, mom, system, steps, ckpt)
+    L = flux_loss(IS, fw, system)
+    if gas_w is not None:
+        L = L + (gas_w[0] * ES).sum() + (gas_w[1] * MS).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    return L.item(), I0.grad, kap.grad, etot.grad, mom.grad
+
+
+def _loss_fwd(system, x, fw, steps, gas_w=None):
+    """The same loss by plain fused steps (no autograd)."""
+    with torch.no_grad():
+        IS, ES, MS = rt_steps(x["I0"], x["kap"], x["etot"], x["mom"], system, steps, steps or 1)
+        L = flux_loss(IS, fw, system)
+        if gas_w is not None:
+            L = L + (gas_w[0] * ES).sum() + (gas_w[1] * MS).sum()
+    return L.item()
+
+
+@pytest.mark.parametrize("K", [24, 80])
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
+def test_fused_step_equals_split_calls_bitwise(dtype, K, layout):
+    p = inp.make_problem(0, n=7, K=K, steps=1)
+    st = p.state
+    system, x = _system(p, dtype, layout)
+    td = rt.torch_dtype(dtype)
+    s = [dict(I=x["I0"].to(td), I2=torch.empty_like(x["I0"].to(td)), vol=_d(st.vol), mom=_d(st.mom),
+              etot=_d(st.etot), T=torch.zeros_like(x["kap"])) for _ in range(2)]
+    a, b = s
+    rt.step(system.mesh, system.params, system.angles, a["I"], a["I2"], a["vol"], system.rho, a["mom"], a["etot"],
+            x["kap"], x["kap"], system.ks, a["T"])
+    rt.transport_step(system.mesh, system.params, system.angles, b["I"], b["I2"], b["vol"])
+    rt.source_implicit(system.mesh, system.params, system.angles, b["I2"], system.rho, b["mom"], b["etot"],
+                       x["kap"], x["kap"], system.ks, b["T"])
+    torch.cuda.synchronize()
+    for k in ("I2", "vol", "mom", "etot", "T"):
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_gradient_matches_oracle():
+    p = inp.make_problem(2, n=8, K=24, steps=5)
+    st = p.state
+    system, x = _system(p)
+    u = inp.loss_face_weights(p.mesh, np.random.default_rng(4))
+    L, gI, gk, _, _ = _grads(system, x, _d(u), p.steps, 2)
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    Lo, gIo, gko = orc.adjoint(om, p.dirs, p.weights, p.phys, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot),
+                               st.rho, st.kP, st.ks, p.steps, u)
+    assert abs(L - Lo) <= 1e-12 * abs(Lo)
+    assert rel_err(gI.cpu().numpy(), gIo) < 1e-10
+    assert rel_err(gk.cpu().numpy(), gko) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_checkpoint_interval_leaves_gradients_unchanged(dtype):
+    p = inp.make_problem(2, n=8, K=48, steps=7)
+    system, x = _system(p, dtype)
+    fw = _d(inp.loss_face_weights(p.mesh, np.random.default_rng(5)))
+    ref = _grads(system, x, fw, p.steps, 1)
+    for ckpt in (2, 3, 7, 10):
+        got = _grads(system, x, fw, p.steps, ckpt)
+        assert got[0] == ref[0]
+        for a, b in zip(got[1:], ref[1:]):
+            assert torch.equal(a, b), ckpt
+
+
+def test_all_input_gradients_match_directional_differences():
+    p = inp.make_problem(2, n=8, K=24, steps=4)
+    system, x = _system(p)
+    rng = np.random.default_rng(6)
+    N, K = p.state.I.shape
+    fw = _d(inp.loss_face_weights(p.mesh, rng))
+    gas_w = (_d(rng.normal(size=N)), _d(rng.normal(size=(N, 3))))
+    L, gI, gk, gE, gM = _grads(system, x, fw, p.steps, 3, gas_w)
+    grads = dict(I0=gI, kap=gk, etot=gE, mom=gM)
+    for key in ("I0", "kap", "etot", "mom"):
+        base = x[key]
+        delta = _d(rng.normal(size=tuple(base.shape))) * base.abs()
+        h = 1e-6
+        xp = dict(x); xp[key] = base + h * delta
+        xm = dict(x); xm[key] = base - h * delta
+        fd = (_loss_fwd(system, xp, fw, p.steps, gas_w) - _loss_fwd(system, xm, fw, p.steps, gas_w)) / (2 * h)
+        an = float((grads[key] * delta).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * abs(L), (key, fd, an)
+
+
+def _loss_term_magnitude(p, u, IS):
+    """S = sum over loss faces of |u_f| 4 pi c A_f sum_k W_k |n_k . n_f| I_up: the scale of
+    the rounding error of one loss evaluation (not an expected value)."""
+    m = p.mesh
+    f = np.nonzero(u)[0]
+    mu = m.face_normal[f] @ p.dirs.T
+    Iup = np.where(mu > 0, IS[m.face_cells[f, 0]], IS[m.face_cells[f, 1]])
+    return 4 * np.pi * p.phys.c_light * float(
+        np.sum(np.abs(u[f]) * m.face_area[f] * np.sum(p.weights * np.abs(mu) * Iup, axis=1)))
+
+
+def test_adjoint_32c_48a_full_size_matches_finite_differences():
+    """Full size of the adjoint workload: 32^3 cells, 48 angles, 20 steps, FP64."""
+    p = inp.make_problem(2)
+    system, x = _system(p)
+    u = inp.loss_face_weights(p.mesh, p.seeds["omega"])
+    fw = _d(u)
+    cells = inp.fd_cells(p.mesh, p.seeds["fd_cells"])
+    L, gI, gk, _, _ = _grads(system, x, fw, p.steps, 8)
+    with torch.no_grad():
+        IS = rt_steps(x["I0"], x["kap"], x["etot"], x["mom"], system, p.steps, p.steps)[0]
+    floor = 64 * np.finfo(np.float64).eps * _loss_term_magnitude(p, u, IS.cpu().numpy())
+    gk = gk.cpu().numpy()
+    gI = gI.cpu().numpy()
+    k_star = p.seeds["fd_cells"].integers(0, p.dirs.shape[0], size=cells.size)
+    assert np.count_nonzero(gk[cells]) > 0
+    kap0 = x["kap"].cpu().numpy()
+    I00 = x["I0"].cpu().numpy()
+    for c, k in zip(cells, k_star):
+        e = 1e-4 * kap0[c]
+        xp, xm = dict(x), dict(x)
+        kp, km = kap0.copy(), kap0.copy(); kp[c] += e; km[c] -= e
+        xp["kap"], xm["kap"] = _d(kp), _d(km)
+        fd = (_loss_fwd(system, xp, fw, p.steps) - _loss_fwd(system, xm, fw, p.steps)) / (2 * e)
+        assert abs(fd - gk[c]) <= 1e-6 * abs(gk[c]) + floor / (2 * e), ("kappa", c, fd, gk[c])
+        e = 1e-3 * I00[c, k]
+        Ip, Im = I00.copy(), I00.copy(); Ip[c, k] += e; Im[c, k] -= e
+        xp, xm = dict(x), dict(x)
+        xp["I0"], xm["I0"] = _d(Ip), _d(Im)
+        fd = (_loss_fwd(system, xp, fw, p.steps) - _loss_fwd(system, xm, fw, p.steps)) / (2 * e)
+        assert abs(fd - gI[c, k]) <= 1e-6 * abs(gI[c, k]) + floor / (2 * e), ("I0", c, k, fd, gI[c, k])
+
+
+def test_fwd_adj_96c_80a_f32_against_f64():
+    """Full size of the checkpointed workload: 96^3 cells, 80 angles, 40 steps, checkpoints every 8."""
+    p = inp.make_problem(4)
+    fw = None
+    res = {}
+    for dtype in (rt.F64, rt.F32):
+        system, x = _system(p, dtype)
+        if fw is None:
+            fw = _d(inp.loss_face_weights(p.mesh, p.seeds["omega"]))
+        L, gI, gk, _, _ = _grads(system, x, fw, p.steps, 8)
+        res[dtype] = (L, gI.cpu().numpy(), gk.cpu().numpy())
+        system.mesh.free()
+        del system, x
+        torch.cuda.empty_cache()
+    L64, gI64, gk64 = res[rt.F64]
+    L32, gI32, gk32 = res[rt.F32]
+    eL, eI, ek = abs(L32 - L64) / abs(L64), rel_err(gI32, gI64), rel_err(gk32, gk64)
+    print(f"f32 vs f64 at 96^3 x 80 x 40: loss {eL:.2e} dL/dI0 {eI:.2e} dL/dkappa {ek:.2e}")
+    assert eL < 1e-5 and eI < 1e-5 and ek < 1e-4
