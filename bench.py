@@ -100,6 +100,83 @@ def run_form(prob, mesh, angles, dtype_code, steps, warmup, log):
                 etot=etot.cpu().numpy())
 
 
+def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
+    """Forward + adjoint throughput on the checkpointed workload (96^3 cells, 80 angles, 40 steps,
+    FP32 transport, checkpoints every 8 steps): cell-angle updates per second of the forward steps,
+    the time covering the forward pass, the recompute and the adjoint of all steps."""
+    import torch
+    from paper_2002_08377_amd import autograd as ag
+    from paper_2002_08377_amd import inputs as inp
+    from paper_2002_08377_amd import rt
+    t0 = time.perf_counter()
+    p = inp.make_problem(4)
+    st, ph = p.state, p.phys
+    N, K = st.I.shape
+    log(f"fwd+adj workload: {N} cells x {K} angles x {p.steps} steps; inputs built in "
+        f"{time.perf_counter() - t0:.1f} s")
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_ADJOINT)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    system = ag.RTSystem(mesh, rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, rt.F32),
+                         rt.AngleSet(p.dirs, p.weights), d(st.rho), d(st.ks), d(st.vol))
+    fw = d(inp.loss_face_weights(p.mesh, p.seeds["omega"]))
+    I0, kap, etot, mom = d(st.I).float(), d(st.kP), d(st.etot), d(st.mom)
+
+    def once():
+        x = [t.clone().requires_grad_() for t in (I0, kap, etot, mom)]
+        IS = ag.rt_steps(*x, system, p.steps, ckpt)[0]
+        ag.flux_loss(IS, fw, system).backward()
+        return x[1].grad
+
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ok = bool(torch.isfinite(g).all())
+    mesh.free()
+    log(f"  fwd+adj: {dt * 1e3:.1f} ms per pass of {p.steps} steps")
+    return {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s", "ms_per_pass": dt * 1e3,
+            "workload": f"adjoint_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p.steps,
+            "checkpoint_every": ckpt, "dtype": "f32", "gradient_finite": ok}
+
+
+def counters_summary(pmc_dir, copy_bytes):
+    """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
+    KiB per dispatch) over a bench run with --copy-calibration; each counter is scaled by what it reads
+    for the calibration kernel (copy_bytes read and copy_bytes written per launch)."""
+    import csv
+    import glob
+    vals = {}
+    for name in ("FETCH_SIZE", "WRITE_SIZE"):
+        for path in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] != name:
+                        continue
+                    kn = r["Kernel_Name"]
+                    key = ("copy" if "neg" in kn else
+                           "step_upwind1_f32" if "k_step<float" in kn else
+                           "step_upwind1_f64" if "k_step<double" in kn else None)
+                    if key:
+                        vals.setdefault((name, key), []).append(float(r["Counter_Value"]) * 1024.0)
+    out = {}
+    scale = {}
+    for name in ("FETCH_SIZE", "WRITE_SIZE"):
+        cp = vals.get((name, "copy"))
+        scale[name] = copy_bytes / float(np.median(cp)) if cp else 1.0
+    for key in ("step_upwind1_f32", "step_upwind1_f64"):
+        fe, wr = vals.get(("FETCH_SIZE", key)), vals.get(("WRITE_SIZE", key))
+        if fe and wr:
+            f_b = float(np.mean(fe)) * scale["FETCH_SIZE"]
+            w_b = float(np.mean(wr)) * scale["WRITE_SIZE"]
+            out[key] = {"fetch_bytes_per_launch": f_b, "write_bytes_per_launch": w_b,
+                        "hbm_bytes_per_launch": f_b + w_b, "launches": len(fe)}
+    return {"source_hash": kernel_source_hash(), "scale": scale, "kernels": out}
+
+
 def cpu_baseline(prob, steps, log):
     """The FP64 oracle (plain C, OpenMP) on the host cores: `steps` full steps of the same workload."""
     import oracle as orc
@@ -122,14 +199,29 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="override cells per side (default 128)")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=10, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--forms", default="f32,f64", help="precision forms to run (f32, f64)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also copy an FP32 intensity-sized array 3 times (a kernel of known traffic, "
-                         "to scale hardware byte counters)")
+                    help="also negate an FP32 intensity-sized array into another 3 times (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
+    ap.add_argument("--no-fwd-adj", action="store_true", help="skip the forward+adjoint measurement")
+    ap.add_argument("--counters-summary", metavar="PMC_DIR",
+                    help="write profiles/traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE output and exit")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.counters_summary:
+        from paper_2002_08377_amd import inputs as inp
+        n = args.n or 128
+        K = inp.CONFIGS[WORKLOAD_INDEX].K
+        summ = counters_summary(args.counters_summary, n ** 3 * K * 4)
+        summ["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'k_step|neg' "
+                           "--output-format csv -- python3 bench.py --steps 2 --warmup 1 --cpu-steps 0 "
+                           "--no-fwd-adj --copy-calibration")
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+            json.dump(summ, f, indent=1)
+        print(json.dumps(summ))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
@@ -151,9 +243,9 @@ def main():
         x = torch.ones(N * K, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
-            y.copy_(x)
+            torch.neg(x, out=y)  # one read and one write of N K 4 bytes, a kernel named for neg
         torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {N * K * 4} bytes")
+        log(f"copy calibration: 3 negated copies of {N * K * 4} bytes")
         del x, y
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
@@ -202,6 +294,8 @@ def main():
         "f32_vs_f64_rel_err_I": err,
     }
     mesh.free()
+    if not args.no_fwd_adj:
+        out["fwd_adj"] = run_fwd_adj(log)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps, log)
     print(json.dumps(out), flush=True)
