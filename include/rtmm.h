@@ -208,7 +208,9 @@ int rt_gradient(rt_mesh *mesh, const rt_params *params, const rt_angles *angles,
  * input), vol_n = V^n, rho, mom_n, etot_n (gas before the source), kP, kJ, ks.
  * Adjoints: lamI [N][K] (dtype) holds dL/dI^{n+1} on entry and dL/dI^n on
  * return; lamE [N] and lamM [N][3] hold dL/d(etot, mom)^{n+1} on entry and
- * dL/d(etot, mom)^n on return; dL_dkP, dL_dkJ [N] are incremented (nullable).
+ * dL/d(etot, mom)^n on return; dL_dkP, dL_dkJ [N] are incremented (nullable;
+ * they may be the same array, which then receives both partials: the gradient
+ * with respect to a tied opacity kP = kJ).
  * The temperature root enters through the implicit function theorem.  Needs a
  * mesh uploaded with RT_MESH_ADJOINT (RT_ESTATE otherwise).
  */
