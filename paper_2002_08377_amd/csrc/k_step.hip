@@ -13,8 +13,10 @@ template <typename T> struct rt_batch { static constexpr int U = 4; };
 template <> struct rt_batch<double> { static constexpr int U = 2; };
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
-// transport of PLM stage 2 (+ source).  Separate instantiations keep each one's
-// registers to what its own loop needs.
+// transport of PLM stage 2 (+ source); 3: the transpose of upwind transport (the
+// adjoint: input lam*/V' per cell and angle, output lam_i = V_i mu_i - sum over the
+// faces the cell is upwind of, g > 0, of g (mu_i - mu_j)).  Separate instantiations
+// keep each one's registers to what its own loop needs.
 //
 // The cells of a workgroup are consecutive, so their half-faces form one contiguous
 // range; it is staged in LDS (dynamic size: the largest range of any workgroup,
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     for (int q = 0; q < APL; ++q) acc[q] = (T)Vn * Ic[q];
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 3) {
       for (int h = h0; h < h1; h += U) {
         // batch metadata; slots past the cell's last face reuse face h0 with a zero record
         int64_t j[U];
@@ -101,10 +103,18 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
           for (int q = 0; q < P; ++q) {
             const T dot = ax * ang.x[q] + ay * ang.y[q] + az * ang.z[q];
             const T g = dot - b;
-            acc[q] -= g * (g > T(0) ? Ic[q] : xn[u][q]);
+            if constexpr (MODE == 1) {
+              acc[q] -= g * (g > T(0) ? Ic[q] : xn[u][q]);
+            } else {
+              acc[q] -= g > T(0) ? g * (Ic[q] - xn[u][q]) : T(0);
+            }
             if (PAIRED) {
               const T g2 = -dot - b;  // the antipodal angle
-              acc[q + P] -= g2 * (g2 > T(0) ? Ic[q + P] : xn[u][q + P]);
+              if constexpr (MODE == 1) {
+                acc[q + P] -= g2 * (g2 > T(0) ? Ic[q + P] : xn[u][q + P]);
+              } else {
+                acc[q + P] -= g2 > T(0) ? g2 * (Ic[q + P] - xn[u][q + P]) : T(0);
+              }
             }
           }
         }
@@ -163,18 +173,25 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
         }
       }
     }
-    const T inv = (T)rt_rcp(Vnew);
+    if constexpr (MODE == 3) {
 #pragma unroll
-    for (int q = 0; q < APL; ++q) Ic[q] = acc[q] * inv;
+      for (int q = 0; q < APL; ++q) Ic[q] = acc[q];
+    } else {
+      const T inv = (T)rt_rcp(Vnew);
+#pragma unroll
+      for (int q = 0; q < APL; ++q) Ic[q] = acc[q] * inv;
+    }
   }
 
-  if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
+  if constexpr (MODE != 3) {
+    if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
+  }
 
   T *Iout = (T *)a.I_out;
 #pragma unroll
   for (int q = 0; q < APL; ++q)
     if (ang.ok[q]) Iout[row + ang.k[q]] = Ic[q];
-  if (MODE != 0 && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
+  if ((MODE == 1 || MODE == 2) && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
 }
 
 // Staging needs (records per half-face) x (half-faces of the largest range of the
@@ -196,6 +213,7 @@ hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
     case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 2: hipLaunchKernelGGL((k_step<T, LPC, APL, 2, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
+    case 3: hipLaunchKernelGGL((k_step<T, LPC, APL, 3, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -512,6 +512,17 @@ int rt_step_adjoint(rt_mesh *m, const rt_params *p, const rt_angles *a, const vo
   s.dt = p->dt;
   hipError_t e = rt_launch_adjoint(s, p->dtype, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+  // transpose of the upwind transport: lam*/V' (written by the source adjoint) in, lam out
+  rt_step_args t = base_args(m, p, a);
+  t.I_in = m->lam_star;
+  t.I_out = lamI;
+  t.vol_in = vol_n;
+  t.vol_out = nullptr;
+  t.do_transport = 3;
+  t.do_source = 0;
+  t.write_gas = 0;
+  e = rt_launch_step(t, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint transport kernel launch");
   return RT_OK;
 }
 

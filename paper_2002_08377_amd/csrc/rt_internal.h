@@ -80,7 +80,8 @@ struct rt_step_args {
   int hf_cap16, hf_cap32, hf_cap64;  // half-faces of the largest range of 16 / 32 / 64 cells
   const uint8_t *wg_order16, *wg_order32, *wg_order64;  // cell order within workgroups
   const uint8_t *wg_order;                              // the one of the launched kernel
-  int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2)
+  int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2),
+                     // 3: transpose of upwind transport (adjoint)
   int do_source;
   int write_gas;
 };
