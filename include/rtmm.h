@@ -192,6 +192,18 @@ int rt_step(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, con
             const double *ks, double *T_new, void *stream);
 
 /*
+ * One RT_UPWIND1 step as rt_step (transport, section 2.2, then the source,
+ * section 2.3, in one fused pass) that also stores the transported intensities,
+ * i.e. the source's input, in I_star [N][K] (device, dtype): the value
+ * rt_step_adjoint needs for this step.  I_out and vol, mom, etot, T_new receive
+ * exactly what rt_step gives.  I_in, I_out and I_star must not overlap.
+ * RT_EINVAL for RT_PLM_VL2.
+ */
+int rt_step_taped(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_in, void *I_out,
+                  void *I_star, double *vol, const double *rho, double *mom, double *etot, const double *kP,
+                  const double *kJ, const double *ks, double *T_new, void *stream);
+
+/*
  * Limited linear reconstruction of every angle (section 2.2 item ii): the
  * Voronoi gradient estimator of S10 with the geometric cell volumes, limited by
  * the Barth-Jespersen factor so that extrapolations from the centre of mass to

@@ -4,11 +4,10 @@ The forward pass advances S first-order steps (transport then implicit source,
 sections 2.2-2.3) with the fused step call and keeps a checkpoint of the state
 (I, E_g, rho v, V) at the start of every segment of `ckpt_every` steps.  The
 backward pass walks the segments in reverse: it restores the segment's
-checkpoint, re-runs its steps with the split transport / source calls, which
-give the same values bit for bit as the fused call, while recording what the
-adjoint of each step needs (the transported intensities I* and the
-start-of-step volume and gas state), and then applies the per-step adjoint in
-reverse order.  Peak memory is therefore one checkpoint per segment plus
+checkpoint, re-runs its steps with the taped step call (the same fused kernel,
+so the same values bit for bit, which also stores the transported intensities
+I*), records the start-of-step volume and gas state, and then applies the
+per-step adjoint in reverse order.  Peak memory is therefore one checkpoint per segment plus
 `ckpt_every` recorded steps, instead of all S steps.
 
 The opacities are tied, kappa_P = kappa_J = kappa_a, so dL/dkappa_a is the sum
@@ -94,6 +93,7 @@ class RTSteps(torch.autograd.Function):
         dk = torch.zeros(N, dtype=torch.float64, device=dev)
         L = ctx.ckpt_every
         tape_I = [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps))]
+        I2 = torch.empty((N, K), dtype=td, device=dev)
         for seg in reversed(range(len(ctx.ckpts))):
             I, etot, mom, vol = (t.clone() for t in ctx.ckpts[seg])
             n0 = seg * L
@@ -101,9 +101,8 @@ class RTSteps(torch.autograd.Function):
             tape = []
             for n in range(nseg):
                 vol_n, mom_n, etot_n = vol.clone(), mom.clone(), etot.clone()
-                rt.transport_step(s.mesh, s.params, s.angles, I, tape_I[n], vol)
-                I.copy_(tape_I[n])
-                rt.source_implicit(s.mesh, s.params, s.angles, I, s.rho, mom, etot, kap, kap, s.ks)
+                rt.step_taped(s.mesh, s.params, s.angles, I, I2, tape_I[n], vol, s.rho, mom, etot, kap, kap, s.ks)
+                I, I2 = I2, I
                 tape.append((tape_I[n], vol_n, mom_n, etot_n))
             for I_star, vol_n, mom_n, etot_n in reversed(tape):
                 rt.step_adjoint(s.mesh, s.params, s.angles, I_star, vol_n, s.rho, mom_n, etot_n, kap, kap, s.ks,

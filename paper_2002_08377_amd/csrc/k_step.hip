@@ -181,6 +181,14 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
 #pragma unroll
       for (int q = 0; q < APL; ++q) Ic[q] = acc[q] * inv;
     }
+    if constexpr (MODE == 1) {
+      if (a.I_star_out) {
+        T *Ist = (T *)a.I_star_out;
+#pragma unroll
+        for (int q = 0; q < APL; ++q)
+          if (ang.ok[q]) Ist[row + ang.k[q]] = Ic[q];
+      }
+    }
   }
 
   if constexpr (MODE != 3) {

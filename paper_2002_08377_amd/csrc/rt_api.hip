@@ -120,7 +120,7 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
 // The transport part of a step; with `src` set, the source follows each stage.
 int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, double *vol,
              const double *rho, double *mom, double *etot, const double *kP, const double *kJ, const double *ks,
-             double *T_new, bool src, hipStream_t st) {
+             double *T_new, bool src, hipStream_t st, void *I_star = nullptr) {
   rt_step_args s = base_args(m, p, a);
   s.rho = rho;
   s.mom = mom;
@@ -131,6 +131,7 @@ int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_i
   if (p->scheme == RT_UPWIND1) {
     s.I_in = I_in;
     s.I_out = I_out;
+    s.I_star_out = I_star;
     s.vol_in = vol;
     s.vol_out = vol;
     s.T_out = T_new;
@@ -460,6 +461,19 @@ int rt_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in
   if ((rc = check_ptrs({I_in, I_out, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
   if (overlap(I_in, I_out, elem(p->dtype) * m->N * a->K)) return fail(RT_EINVAL, "I_in and I_out overlap");
   return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream);
+}
+
+int rt_step_taped(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, void *I_star,
+                  double *vol, const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
+                  const double *ks, double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I_in, I_out, I_star, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
+  if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "rt_step_taped covers RT_UPWIND1 steps only");
+  const size_t bytes = elem(p->dtype) * m->N * a->K;
+  if (overlap(I_in, I_out, bytes) || overlap(I_in, I_star, bytes) || overlap(I_out, I_star, bytes))
+    return fail(RT_EINVAL, "I_in, I_out and I_star must not overlap");
+  return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream, I_star);
 }
 
 int rt_gradient(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, void *grad, void *stream) {

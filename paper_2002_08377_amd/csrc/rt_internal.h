@@ -61,6 +61,8 @@ struct rt_step_args {
   const void *I_half;  // PLM stage 2: half-step intensities (face states)
   const void *grad;    // PLM stage 2: limited gradients of I_half
   void *I_out;
+  void *I_star_out;    // upwind with source: when set, the transported intensities (the
+                       // source's input) are stored here as well
   const double *vol_in;
   double *vol_out;
   const double *rho;

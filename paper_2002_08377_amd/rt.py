@@ -58,6 +58,7 @@ _SIGS = {
     "rt_transport_step": [ctypes.c_void_p] * 7,
     "rt_source_implicit": [ctypes.c_void_p] * 12,
     "rt_step": [ctypes.c_void_p] * 14,
+    "rt_step_taped": [ctypes.c_void_p] * 15,
     "rt_gradient": [ctypes.c_void_p] * 6,
     "rt_step_adjoint": [ctypes.c_void_p] * 17,
     "rt_flux_loss": [ctypes.c_void_p] * 8,
@@ -245,6 +246,16 @@ def step(mesh, params, angles, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_n
                        *_gas(mesh, rho, mom, etot, kP, kJ, ks), _dev(T_new, torch.float64, (N,), "T_new", True),
                        _stream(stream))
     _check("rt_step", rc)
+
+
+def step_taped(mesh, params, angles, I_in, I_out, I_star, vol, rho, mom, etot, kP, kJ, ks, T_new=None, stream=None):
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    rc = lib().rt_step_taped(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), _dev(I_in, td, (N, K), "I_in"),
+                             _dev(I_out, td, (N, K), "I_out"), _dev(I_star, td, (N, K), "I_star"),
+                             _dev(vol, torch.float64, (N,), "vol"), *_gas(mesh, rho, mom, etot, kP, kJ, ks),
+                             _dev(T_new, torch.float64, (N,), "T_new", True), _stream(stream))
+    _check("rt_step_taped", rc)
 
 
 def gradient(mesh, params, angles, I, grad, stream=None):

@@ -1,8 +1,9 @@
 """Differentiable radiation steps with checkpoint / recompute, through the C ABI.
 
-* The recompute of the backward pass uses the split transport / source calls
-  while the forward pass uses the fused step: the two must agree bit for bit,
-  in both precision forms and in the paired and general lane layouts.
+* The recompute of the backward pass uses the taped step, which must give the
+  fused step's values bit for bit and store the transported intensities exactly
+  as the transport call alone gives them; fused and split calls also agree bit
+  for bit, in both precision forms and in the paired and general lane layouts.
 * The gradient of the emergent-flux loss through `RTSteps` (FP64) matches the
   oracle's hand-written reverse mode to 1e-10 (normwise) and the loss to 1e-12.
 * The checkpoint interval changes memory, never values: gradients are equal bit
@@ -85,6 +86,44 @@ def test_fused_step_equals_split_calls_bitwise(dtype, K, layout):
     torch.cuda.synchronize()
     for k in ("I2", "vol", "mom", "etot", "T"):
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("K", [24, 80])
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_taped_step_equals_step_and_records_transport(dtype, K):
+    p = inp.make_problem(0, n=7, K=K, steps=1)
+    st = p.state
+    system, x = _system(p, dtype)
+    td = rt.torch_dtype(dtype)
+    s = [dict(I=x["I0"].to(td), I2=torch.empty_like(x["I0"].to(td)), vol=_d(st.vol), mom=_d(st.mom),
+              etot=_d(st.etot), T=torch.zeros_like(x["kap"])) for _ in range(2)]
+    a, b = s
+    Istar = torch.full_like(a["I"], float("nan"))
+    Itr = torch.empty_like(a["I"])
+    vtr = _d(st.vol)
+    rt.step(system.mesh, system.params, system.angles, a["I"], a["I2"], a["vol"], system.rho, a["mom"], a["etot"],
+            x["kap"], x["kap"], system.ks, a["T"])
+    rt.step_taped(system.mesh, system.params, system.angles, b["I"], b["I2"], Istar, b["vol"], system.rho, b["mom"],
+                  b["etot"], x["kap"], x["kap"], system.ks, b["T"])
+    rt.transport_step(system.mesh, system.params, system.angles, x["I0"].to(td), Itr, vtr)
+    torch.cuda.synchronize()
+    for k in ("I2", "vol", "mom", "etot", "T"):
+        assert torch.equal(a[k], b[k]), k
+    assert torch.equal(Istar, Itr)
+
+
+def test_taped_step_rejects_overlap_and_plm():
+    p = inp.make_problem(0, n=7, K=24, steps=1)
+    system, x = _system(p)
+    I = x["I0"].clone()
+    I2 = torch.empty_like(I)
+    with pytest.raises(rt.RTError):
+        rt.step_taped(system.mesh, system.params, system.angles, I, I2, I, _d(p.state.vol), system.rho,
+                      x["mom"].clone(), x["etot"].clone(), x["kap"], x["kap"], system.ks)
+    plm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, p.dt, rt.F64, rt.PLM_VL2)
+    with pytest.raises(rt.RTError):
+        rt.step_taped(system.mesh, plm, system.angles, I, I2, torch.empty_like(I), _d(p.state.vol), system.rho,
+                      x["mom"].clone(), x["etot"].clone(), x["kap"], x["kap"], system.ks)
 
 
 def test_gradient_matches_oracle():
