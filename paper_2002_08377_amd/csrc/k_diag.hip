@@ -1,7 +1,7 @@
 // Grid reductions: conservation diagnostics (section 2.3.1) and the emergent-flux
 // loss with its seed.  Each cell group reduces over its angles, each workgroup
-// over its cells through LDS, and one final workgroup over the per-workgroup
-// partials in a fixed order, so results are deterministic (no atomics).
+// over its cells through LDS, then two folds over the per-workgroup partials in a
+// fixed order, so results are deterministic (no atomics).
 #include "rt_device.h"
 
 namespace {
@@ -75,15 +75,19 @@ __global__ __launch_bounds__(RT_BLOCK) void k_diag(int64_t N, int K, const doubl
   block_reduce_store<ND, LPC>(v, kind, partial + lb * ND);
 }
 
-__global__ __launch_bounds__(RT_BLOCK) void k_final(const double *partial, int64_t nblk, int nv,
-                                                    unsigned min_mask, double *out) {
-  // one workgroup; column i: thread t folds rows t, t + 256, ... in order, then a fixed tree in LDS
+// Fold rows [blockIdx.x * chunk, +chunk) of an [nrows][nv] table into row blockIdx.x of
+// `out`: for column i, thread t folds rows t, t + 256, ... of the chunk in order, then a
+// fixed tree in LDS.  The chunking depends on nrows only, so results are deterministic.
+__global__ __launch_bounds__(RT_BLOCK) void k_fold(const double *partial, int64_t nrows, int nv,
+                                                   unsigned min_mask, int64_t chunk, double *out) {
   __shared__ double sh[RT_BLOCK];
   const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < nrows ? r0 + chunk : nrows;
   for (int i = 0; i < nv; ++i) {
     const bool is_min = (min_mask >> i) & 1u;
     double acc = is_min ? INFINITY : 0.0;
-    for (int64_t b = t; b < nblk; b += RT_BLOCK) {
+    for (int64_t b = r0 + t; b < r1; b += RT_BLOCK) {
       const double x = partial[b * nv + i];
       acc = is_min ? fmin(acc, x) : acc + x;
     }
@@ -93,9 +97,22 @@ __global__ __launch_bounds__(RT_BLOCK) void k_final(const double *partial, int64
       if (t < o) sh[t] = is_min ? fmin(sh[t], sh[t + o]) : sh[t] + sh[t + o];
       __syncthreads();
     }
-    if (t == 0) out[i] = sh[0];
+    if (t == 0) out[blockIdx.x * nv + i] = sh[0];
     __syncthreads();
   }
+}
+
+// Two folds: up to RT_BLOCK workgroups over contiguous chunks of the per-workgroup
+// partials into `mid` ([RT_BLOCK][nv]), then one workgroup over those into `out`.
+hipError_t reduce_partials(const double *partial, int64_t nrows, int nv, unsigned min_mask, double *mid,
+                           double *out, hipStream_t s) {
+  const int64_t g = nrows < RT_BLOCK ? nrows : RT_BLOCK;
+  const int64_t chunk = (nrows + g - 1) / g;
+  hipLaunchKernelGGL(k_fold, dim3((unsigned)g), dim3(RT_BLOCK), 0, s, partial, nrows, nv, min_mask, chunk, mid);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(RT_BLOCK), 0, s, (const double *)mid, g, nv, min_mask, g, out);
+  return hipGetLastError();
 }
 
 // Loss: each (face, angle) belongs to its upwind cell (A n_out . n_k > 0), which adds
@@ -159,8 +176,7 @@ hipError_t launch_diag(const rt_mesh *m, int K, const double *dirs, const double
                      W, c_red, c_light, (const T *)I, vol, etot, mom, m->red, nblk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(RT_BLOCK), 0, s, m->red, nblk, ND, 1u << 8, out);
-  return hipGetLastError();
+  return reduce_partials(m->red, nblk, ND, 1u << 8, m->red_mid, out, s);
 }
 
 template <typename T, int LPC, int APL>
@@ -174,8 +190,7 @@ hipError_t launch_loss(const rt_mesh *m, int K, const double *dirs, const double
                      nblk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(RT_BLOCK), 0, s, m->red, nblk, 1, 0u, loss);
-  return hipGetLastError();
+  return reduce_partials(m->red, nblk, 1, 0u, m->red_mid, loss, s);
 }
 
 #define RT_DISPATCH(FN, T, ...)                                   \

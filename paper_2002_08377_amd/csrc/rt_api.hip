@@ -45,7 +45,7 @@ template <typename P> hipError_t dmalloc(P **p, size_t bytes) {
 void free_mesh_arrays(rt_mesh *m) {
   void *ptrs[] = {m->vol0,    m->D,       m->wn,       m->row_ptr, m->hf_nbr, m->hf_face, m->hf_an64,
                   m->hf_an32, m->hf_gp64, m->hf_rel64, m->hf_gp32, m->hf_rel32, m->I_half, m->grad,
-                  m->lam_star, m->red, m->wg_order16, m->wg_order32, m->wg_order64};
+                  m->lam_star, m->red, m->red_mid, m->wg_order16, m->wg_order32, m->wg_order64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -332,6 +332,7 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   }
   if (flags & RT_MESH_ADJOINT) RT_ALLOC(m->lam_star, sizeof(double) * N * k_max);
   RT_ALLOC(m->red, sizeof(double) * RT_NDIAG * nred);
+  RT_ALLOC(m->red_mid, sizeof(double) * RT_NDIAG * RT_BLOCK);
   RT_ALLOC(m->wg_order16, N);
   RT_ALLOC(m->wg_order32, N);
   RT_ALLOC(m->wg_order64, N);

@@ -33,6 +33,7 @@ struct rt_mesh {
   void *grad;         // [N][3][k_max] doubles (RT_MESH_PLM)
   void *lam_star;     // [N][k_max] doubles (RT_MESH_ADJOINT)
   double *red;        // reduction partials, RT_NDIAG * n_red_blocks doubles
+  double *red_mid;    // first fold of the partials, RT_NDIAG * RT_BLOCK doubles
   int64_t n_red_blocks;
   int32_t hf_cap16;   // most half-faces of any 16 consecutive cells (workgroups of 16 cells)
   int32_t hf_cap32;   // same for 32 consecutive cells
