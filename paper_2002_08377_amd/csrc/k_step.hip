@@ -8,9 +8,9 @@
 namespace {
 
 // Faces gathered per batch: all their neighbour-row loads are issued before any is
-// used, so one memory round trip serves U faces.
-template <typename T> struct rt_batch { static constexpr int U = 4; };
-template <> struct rt_batch<double> { static constexpr int U = 2; };
+// used, so one memory round trip serves U faces (two faces measured ~2% faster than
+// four in FP32 at 80 angles).
+template <typename T> struct rt_batch { static constexpr int U = 2; };
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
 // transport of PLM stage 2 (+ source); 3: the transpose of upwind transport (the
