@@ -156,6 +156,53 @@ def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
             "checkpoint_every": ckpt, "dtype": "f32", "gradient_finite": ok}
 
 
+def run_plm(log):
+    """The PLM workload (64^3 cells, 80 angles, 100 van Leer steps, optical depths 1e-3..1e3 per
+    cell): throughput of both precision forms, and the total-energy drift over the 100 steps of
+    the same workload on a still mesh (with moving faces the gas energy density is not advected
+    with the cell volumes, hydrodynamics being outside the step, so only a still mesh conserves
+    sum V (E_g + (c/cbar) E_r) exactly)."""
+    import torch
+    from paper_2002_08377_amd import inputs as inp
+    from paper_2002_08377_amd import rt
+    p = inp.make_problem(1)
+    st, ph = p.state, p.phys
+    N, K = st.I.shape
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    angles = rt.AngleSet(p.dirs, p.weights)
+    out = {"workload": f"plm_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p.steps,
+           "scheme": "plm_vl2"}
+    for still in (False, True):
+        w = np.zeros_like(st.mesh_vel) if still else st.mesh_vel
+        mesh = rt.Mesh.from_inputs(p.mesh, w, k_max=K, flags=rt.MESH_PLM)
+        for name, code in (("f64", rt.F64), ("f32", rt.F32)):
+            prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, code, rt.PLM_VL2)
+            td = rt.torch_dtype(code)
+            I = d(st.I).to(td)
+            I2 = torch.empty_like(I)
+            vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+            rho, kP, kJ, ks = d(st.rho), d(st.kP), d(st.kJ), d(st.ks)
+            d0 = rt.diagnostics(mesh, prm, angles, I, vol, etot, mom)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(p.steps):
+                rt.step(mesh, prm, angles, I, I2, vol, rho, mom, etot, kP, kJ, ks)
+                I, I2 = I2, I
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            d1 = rt.diagnostics(mesh, prm, angles, I, vol, etot, mom)
+            if still:
+                e0, e1 = d0[0] + d0[1], d1[0] + d1[1]
+                out.setdefault("energy_drift_still_mesh", {})[name] = abs(e1 - e0) / e0
+            else:
+                out[name] = {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s",
+                             "ms_per_step": dt * 1e3 / p.steps}
+                log(f"  plm {name}: {dt * 1e3 / p.steps:.3f} ms/step")
+        mesh.free()
+    log(f"  plm energy drift over {p.steps} steps (still mesh): {out['energy_drift_still_mesh']}")
+    return out
+
+
 def counters_summary(pmc_dir, copy_bytes):
     """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch) over a bench run with --copy-calibration; each counter is scaled by what it reads
@@ -218,6 +265,7 @@ def main():
                     help="also negate an FP32 intensity-sized array into another 3 times (a kernel of known "
                          "traffic, to scale hardware byte counters)")
     ap.add_argument("--no-fwd-adj", action="store_true", help="skip the forward+adjoint measurement")
+    ap.add_argument("--no-plm", action="store_true", help="skip the PLM throughput / energy-drift measurement")
     ap.add_argument("--counters-summary", metavar="PMC_DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE output and exit")
     ap.add_argument("--quiet", action="store_true")
@@ -230,7 +278,7 @@ def main():
         summ = counters_summary(args.counters_summary, n ** 3 * K * 4)
         summ["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'k_step|neg' "
                            "--output-format csv -- python3 bench.py --steps 2 --warmup 1 --cpu-steps 0 "
-                           "--no-fwd-adj --copy-calibration")
+                           "--no-fwd-adj --no-plm --copy-calibration")
         with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
             json.dump(summ, f, indent=1)
         print(json.dumps(summ))
@@ -322,6 +370,8 @@ def main():
     mesh.free()
     if not args.no_fwd_adj:
         out["fwd_adj"] = run_fwd_adj(log)
+    if not args.no_plm:
+        out["plm"] = run_plm(log)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps, log)
     print(json.dumps(out), flush=True)

@@ -71,10 +71,12 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   if (MODE != 0) {
     // ---- transport: charges V I minus the upwind charge through every face -------------
     const double Vn = a.vol_in[cell];
-    Vnew = Vn + a.dt * a.D[cell];
+    const double dV = a.dt * a.D[cell];
+    Vnew = Vn + dV;
+    // the charge through the faces is accumulated apart from V I (the transpose adds V mu)
     T acc[APL];
 #pragma unroll
-    for (int q = 0; q < APL; ++q) acc[q] = (T)Vn * Ic[q];
+    for (int q = 0; q < APL; ++q) acc[q] = MODE == 3 ? (T)Vn * Ic[q] : T(0);
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
     if (MODE == 1 || MODE == 3) {
@@ -177,9 +179,13 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
 #pragma unroll
       for (int q = 0; q < APL; ++q) Ic[q] = acc[q];
     } else {
-      const T inv = (T)rt_rcp(Vnew);
+      // I' = I (V/V') + (charge through the faces)/V'.  The ratio V/V' = 1 - dt D/V' is
+      // formed in FP64, so on a still mesh it is exactly one: the stored intensities then
+      // carry no per-cell rounding of V that would repeat, with one sign, every step.
+      const double iV = rt_rcp(Vnew);
+      const T cr = (T)(1.0 - dV * iV), ci = (T)iV;
 #pragma unroll
-      for (int q = 0; q < APL; ++q) Ic[q] = acc[q] * inv;
+      for (int q = 0; q < APL; ++q) Ic[q] = Ic[q] * cr + acc[q] * ci;
     }
     if constexpr (MODE == 1) {
       if (a.I_star_out) {

@@ -286,3 +286,18 @@ def test_eight_byte_aligned_arrays(dtype):
     torch.cuda.synchronize()
     assert I_u.data_ptr() % 16 != 0
     assert rel_err(dp.host(O_u), dp.host(dp.I2)) < (1e-14 if dtype == rt.F64 else 1e-6)
+
+
+def test_plm_64c_80a_100_steps_energy_drift():
+    """The PLM workload at full size (64^3 cells, 80 angles, 100 steps) on a still mesh: the
+    total energy sum V (E_g + (c/cbar) E_r) drifts by at most 1e-10 (relative) in FP64."""
+    p = inp.make_problem(1)
+    st = p.state
+    p.state.mesh_vel = np.zeros_like(st.mesh_vel)
+    dp = DeviceProblem(p, scheme=rt.PLM_VL2)
+    d0 = rt.diagnostics(dp.mesh, dp.params, dp.angles, dp.I, dp.vol, dp.etot, dp.mom)
+    dp.run_gpu(p.steps)
+    d1 = rt.diagnostics(dp.mesh, dp.params, dp.angles, dp.I, dp.vol, dp.etot, dp.mom)
+    e0, e1 = d0[0] + d0[1], d1[0] + d1[1]
+    assert abs(e1 - e0) <= 1e-10 * e0
+    assert d1[9] == 0 and d1[8] > 0
