@@ -209,7 +209,10 @@ int rt_step_taped(rt_mesh *mesh, const rt_params *params, const rt_angles *angle
  * the Barth-Jespersen factor so that extrapolations from the centre of mass to
  * every face centroid stay within the range of the cell and its neighbours.
  * I [N][K] (device, dtype) in, grad [N][3][K] (device, dtype) out.  Needs
- * RT_MESH_PLM only for the scheme, not for this call.
+ * RT_MESH_PLM only for the scheme, not for this call.  The face records of 16
+ * consecutive cells are staged in 64 KiB of LDS: RT_EHIP if such a block has more
+ * than 655 half-faces in FP64 (1260 in FP32), about 40 faces per cell, far above
+ * the ~16 of a Voronoi mesh.
  */
 int rt_gradient(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I, void *grad,
                 void *stream);

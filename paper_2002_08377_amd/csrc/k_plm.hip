@@ -5,21 +5,48 @@
 // then the Barth-Jespersen factor alpha = min(1, (max - phi)/max_f delta_f,
 // (min - phi)/min_f delta_f) over the extrapolations delta_f = grad.(r~_f - s_i),
 // with max/min over the cell and its face neighbours.  Taking the largest and
-// smallest delta is exact: IEEE division is monotone in the divisor.
+// smallest delta and dividing once matches taking the minimum of the per-face
+// ratios (division is monotone in the divisor; the reciprocal here is refined to
+// within an ulp).
 #include "rt_device.h"
 
 namespace {
 
+// The workgroup's cells are consecutive, so their half-faces form one contiguous range;
+// its records (the two estimator vectors, the extrapolation offset and the neighbour)
+// are staged in LDS once and every lane group reads them from there.  Neighbour rows
+// are gathered two faces per batch, all loads of a batch issued before any is used.
 template <typename T, int LPC, int APL>
 __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ hf_nbr, const void *hf_gp,
                                                        const void *hf_rel, const double *__restrict__ vol0,
-                                                       const T *__restrict__ I, T *__restrict__ G, int64_t nblk) {
+                                                       const T *__restrict__ I, T *__restrict__ G, int hf_cap,
+                                                       int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
+  constexpr int U = 2;
+  constexpr int CPB = RT_BLOCK / LPC;
+  extern __shared__ __align__(16) unsigned char rt_smem[];
+  V4 *s_gp = (V4 *)rt_smem;        // [hf_cap][2]
+  V4 *s_rel = s_gp + 2 * hf_cap;   // [hf_cap]: r~_f - s_i
+  int32_t *s_nbr = (int32_t *)(s_rel + hf_cap);
   const int64_t lb = rt_logical_block(nblk);
   if (lb < 0) return;
-  constexpr int CPB = RT_BLOCK / LPC;
-  const int64_t cell = lb * CPB + threadIdx.x / LPC;
+  const int64_t c0 = lb * CPB;
+  const int64_t c1 = c0 + CPB < N ? c0 + CPB : N;
+  const int H0 = row_ptr[c0];
+  {
+    const V4 *gp = (const V4 *)hf_gp;
+    const V4 *rel = (const V4 *)hf_rel;
+    const int nH = row_ptr[c1] - H0;  // <= hf_cap by construction
+    for (int i = threadIdx.x; i < nH; i += RT_BLOCK) {
+      s_gp[2 * i] = gp[2 * (H0 + i)];
+      s_gp[2 * i + 1] = gp[2 * (H0 + i) + 1];
+      s_rel[i] = rel[2 * (H0 + i)];
+      s_nbr[i] = hf_nbr[H0 + i];
+    }
+  }
+  __syncthreads();
+  const int64_t cell = c0 + threadIdx.x / LPC;
   if (cell >= N) return;
   const int l = threadIdx.x % LPC;
   int kk[APL];
@@ -35,25 +62,39 @@ __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const i
     gx[q] = gy[q] = gz[q] = T(0);
     lo[q] = hi[q] = s[q];
   }
-  const V4 *gp = (const V4 *)hf_gp;
-  const V4 *rel = (const V4 *)hf_rel;
   const int h0 = row_ptr[cell], h1 = row_ptr[cell + 1];
-  for (int h = h0; h < h1; ++h) {
-    const int64_t j = hf_nbr[h];
-    const V4 p0 = gp[2 * h], p1 = gp[2 * h + 1];
-    const T *Ij = I + j * K;
+  for (int h = h0; h < h1; h += U) {
+    // slots past the cell's last face repeat its first face with zero weights; they
+    // leave the sums unchanged and re-read a neighbour already in the min/max
+    int64_t j[U];
+    V4 p0[U], p1[U];
 #pragma unroll
-    for (int q = 0; q < APL; ++q) {
-      const T o = Ij[kk[q]];
-      const T d = o - s[q], t = s[q] + o;
-      gx[q] += d * p0.x + t * p0.w;
-      gy[q] += d * p0.y + t * p1.x;
-      gz[q] += d * p0.z + t * p1.y;
-      lo[q] = fmin(lo[q], o);
-      hi[q] = fmax(hi[q], o);
+    for (int u = 0; u < U; ++u) {
+      const bool v = h + u < h1;
+      const int i = (v ? h + u : h0) - H0;
+      j[u] = s_nbr[i];
+      p0[u] = s_gp[2 * i];
+      p1[u] = s_gp[2 * i + 1];
+      if (!v) p0[u] = p1[u] = V4{T(0), T(0), T(0), T(0)};
     }
+    T o[U][APL];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < APL; ++q) o[u][q] = I[j[u] * K + kk[q]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < APL; ++q) {
+        const T d = o[u][q] - s[q], t = s[q] + o[u][q];
+        gx[q] += d * p0[u].x + t * p0[u].w;
+        gy[q] += d * p0[u].y + t * p1[u].x;
+        gz[q] += d * p0[u].z + t * p1[u].y;
+        lo[q] = fmin(lo[q], o[u][q]);
+        hi[q] = fmax(hi[q], o[u][q]);
+      }
   }
-  const T iv = (T)(1.0 / vol0[cell]);
+  const T iv = (T)rt_rcp(vol0[cell]);
   T dmax[APL], dmin[APL];
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
@@ -63,7 +104,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const i
     dmax[q] = dmin[q] = T(0);
   }
   for (int h = h0; h < h1; ++h) {
-    const V4 r0 = rel[2 * h];
+    const V4 r0 = s_rel[h - H0];
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
       const T dl = gx[q] * r0.x + gy[q] * r0.y + gz[q] * r0.z;
@@ -75,8 +116,8 @@ __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const i
   for (int q = 0; q < APL; ++q) {
     if (!ok[q]) continue;
     T al = T(1);
-    if (dmax[q] > T(0)) al = fmin(al, (hi[q] - s[q]) / dmax[q]);
-    if (dmin[q] < T(0)) al = fmin(al, (lo[q] - s[q]) / dmin[q]);
+    if (dmax[q] > T(0)) al = fmin(al, (hi[q] - s[q]) * rt_rcp_refined(dmax[q]));
+    if (dmin[q] < T(0)) al = fmin(al, (lo[q] - s[q]) * rt_rcp_refined(dmin[q]));
     const int k = kk[q];
     G[(cell * 3 + 0) * K + k] = al * gx[q];
     G[(cell * 3 + 1) * K + k] = al * gy[q];
@@ -86,40 +127,49 @@ __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const i
 
 template <typename T, int LPC, int APL>
 hipError_t launch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+  using V4 = typename rt_vec4<T>::type;
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (m->N + cpb - 1) / cpb;
   const void *gp = std::is_same<T, double>::value ? (const void *)m->hf_gp64 : (const void *)m->hf_gp32;
   const void *rel = std::is_same<T, double>::value ? (const void *)m->hf_rel64 : (const void *)m->hf_rel32;
-  hipLaunchKernelGGL((k_gradient<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K,
-                     m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, nblk);
+  const int cap = cpb == 16 ? m->hf_cap16 : m->hf_cap32;
+  const size_t smem = (3 * sizeof(V4) + sizeof(int32_t)) * (size_t)cap;
+  if (smem > 65536) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_gradient<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s, m->N,
+                     K, m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, cap, nblk);
   return hipGetLastError();
 }
 
-template <typename T> hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
-  if (K % 16 == 0 || K > 64) {
-    switch ((K + 15) / 16) {
-      case 1: return launch<T, 16, 1>(m, K, I, G, s);
-      case 2: return launch<T, 16, 2>(m, K, I, G, s);
-      case 3: return launch<T, 16, 3>(m, K, I, G, s);
-      case 4: return launch<T, 16, 4>(m, K, I, G, s);
-      case 5: return launch<T, 16, 5>(m, K, I, G, s);
-      case 6: return launch<T, 16, 6>(m, K, I, G, s);
-      case 7: return launch<T, 16, 7>(m, K, I, G, s);
-      case 8: return launch<T, 16, 8>(m, K, I, G, s);
-    }
-  } else {
-    switch ((K + 7) / 8) {
-      case 1: return launch<T, 8, 1>(m, K, I, G, s);
-      case 2: return launch<T, 8, 2>(m, K, I, G, s);
-      case 3: return launch<T, 8, 3>(m, K, I, G, s);
-      case 4: return launch<T, 8, 4>(m, K, I, G, s);
-      case 5: return launch<T, 8, 5>(m, K, I, G, s);
-      case 6: return launch<T, 8, 6>(m, K, I, G, s);
-      case 7: return launch<T, 8, 7>(m, K, I, G, s);
-      case 8: return launch<T, 8, 8>(m, K, I, G, s);
-    }
+template <typename T> hipError_t dispatch16(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+  switch ((K + 15) / 16) {
+    case 1: return launch<T, 16, 1>(m, K, I, G, s);
+    case 2: return launch<T, 16, 2>(m, K, I, G, s);
+    case 3: return launch<T, 16, 3>(m, K, I, G, s);
+    case 4: return launch<T, 16, 4>(m, K, I, G, s);
+    case 5: return launch<T, 16, 5>(m, K, I, G, s);
+    case 6: return launch<T, 16, 6>(m, K, I, G, s);
+    case 7: return launch<T, 16, 7>(m, K, I, G, s);
+    case 8: return launch<T, 16, 8>(m, K, I, G, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Small angle sets take 8 lanes per cell (32-cell workgroups); if their half-face
+// records do not fit in LDS, 16 lanes (16-cell workgroups) halve the staging.
+template <typename T> hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+  if (K % 16 == 0 || K > 64) return dispatch16<T>(m, K, I, G, s);
+  hipError_t e = hipErrorInvalidValue;
+  switch ((K + 7) / 8) {
+    case 1: e = launch<T, 8, 1>(m, K, I, G, s); break;
+    case 2: e = launch<T, 8, 2>(m, K, I, G, s); break;
+    case 3: e = launch<T, 8, 3>(m, K, I, G, s); break;
+    case 4: e = launch<T, 8, 4>(m, K, I, G, s); break;
+    case 5: e = launch<T, 8, 5>(m, K, I, G, s); break;
+    case 6: e = launch<T, 8, 6>(m, K, I, G, s); break;
+    case 7: e = launch<T, 8, 7>(m, K, I, G, s); break;
+    case 8: e = launch<T, 8, 8>(m, K, I, G, s); break;
+  }
+  return e == hipErrorInvalidConfiguration ? dispatch16<T>(m, K, I, G, s) : e;
 }
 
 }  // namespace

@@ -87,6 +87,13 @@ __device__ __forceinline__ double rt_rcp(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rt_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Reciprocal within an ulp in either precision (FP32: the estimate refined by one
+// Newton step), for ratios that decide a limiter.
+__device__ __forceinline__ double rt_rcp_refined(double x) { return rt_rcp(x); }
+__device__ __forceinline__ float rt_rcp_refined(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
 
 // Angles of a lane: k = l + LPC * q for q < APL; ok[q] false past K.  With FULL
 // (K == LPC * APL) every angle is live and k needs no clamping.
