@@ -73,6 +73,7 @@ def _load():
             "or_diagnostics": [I64, INT, P, P, D, D, P, P, P, P, P],
             "or_transport_upwind_vjp": [MP, P, INT, P, D, D, P, P, P, P],
             "or_source_vjp": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P, P, P, P, P],
+            "or_marked_cells": [I64, P, P, P, P, P, D, INT, P, D, D, D, D, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -343,3 +344,23 @@ def adjoint(om: OracleMesh, dirs, W, phys, dt, st0: OState, rho, kappa_a, ks, st
         dk += dkP + dkJ
         lamI = transport_upwind_vjp(om, dirs, phys.c_red, dt, vol, lamI)
     return L, lamI, dk
+
+
+RT_CELL_BOUNDARY = 1
+RT_CELL_EMITTER = 2
+
+
+def marked_cells(dirs, phys, dt, st: OState, rho, kP, cells, kinds, T_eff, direction, cos_open, tau):
+    """Boundary and emitter cells (sections 2.4-2.5) applied after a step; returns a new OState.
+
+    cells, kinds [n] int; T_eff, cos_open [n]; direction [n][3] unit vectors; tau > 0."""
+    out = st.copy()
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+    assert np.unique(cells).size == cells.size, "marked cells must be distinct"
+    K = out.I.shape[1]
+    _load().or_marked_cells(cells.size, _p(cells), _p(kinds), _p(_f64(T_eff)), _p(_f64(direction)),
+                            _p(_f64(cos_open)), float(tau), K, _p(_f64(dirs)), phys.c_red, phys.c_light,
+                            phys.a_rad, float(dt), _p(out.I), _p(_f64(rho)), _p(out.mom), _p(out.etot),
+                            _p(_f64(kP)))
+    return out

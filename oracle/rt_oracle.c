@@ -671,3 +671,65 @@ void or_source_vjp(int64_t N, int K, const double *dirs, const double *W, double
   }
 }
 #endif
+
+#ifndef OR_COMPLEX
+/*
+ * Marked cells (sections 2.4 and 2.5), applied after a step.  Marked cell m is
+ * cell[m] of kind[m] with radiation temperature T_eff[m], a unit direction dir[m]
+ * and an opening cosine cos_open[m]; its directions "of interest" are the angles
+ * with n_k . dir >= cos_open (READING: the paper selects the directions of a source
+ * by an opening angle around a user direction).  S = a T_eff^4 / 4 pi.
+ *  kind 1, boundary (section 2.4, the discretised relaxation with f = min(dt/tau, 1)):
+ *    I_k <- I_k - (I_k - I0_k) f, with I0_k = S for the directions of interest and 0
+ *    otherwise (an absorbing boundary when no direction is of interest);
+ *    rho v <- rho v (1 - f), and the gas total energy loses the kinetic energy that
+ *    goes with it (READING: the energy term the paper leaves to the reader; the
+ *    density is not evolved by the radiation step, so its relaxation is not applied).
+ *  kind 2, emitter (section 2.5): for the directions of interest only, the comoving
+ *    emission-absorption term at T_eff, integrated implicitly over dt like eq. 28
+ *    (READING: the paper gives the continuous form only):
+ *      Gamma = gamma (1 - v.n/c), I~ = Gamma^4 I, x = dt Gamma cbar rho kP,
+ *      I~' = (I~ + x S) / (1 + x), I' = I~' / Gamma^4;
+ *    the gas is not changed (the source is external).
+ * Cells are distinct; the others are untouched.
+ */
+void or_marked_cells(int64_t n, const int32_t *cell, const int32_t *kind, const double *T_eff, const double *dir,
+                     const double *cos_open, double tau, int K, const double *dirs, double c_red, double c_light,
+                     double a_rad, double dt, double *I, const double *rho, double *mom, double *etot,
+                     const double *kP) {
+  const double f = dt / tau < 1.0 ? dt / tau : 1.0;
+  for (int64_t m = 0; m < n; ++m) {
+    const int64_t i = cell[m];
+    const double T2 = T_eff[m] * T_eff[m];
+    const double S = a_rad * T2 * T2 / (4.0 * OR_PI);
+    const double *d = dir + 3 * m;
+    double *Ii = I + i * K;
+    if (kind[m] == 1) {
+      for (int k = 0; k < K; ++k) {
+        const double nd = dirs[3 * k] * d[0] + dirs[3 * k + 1] * d[1] + dirs[3 * k + 2] * d[2];
+        const double I0 = nd >= cos_open[m] ? S : 0.0;
+        Ii[k] -= (Ii[k] - I0) * f;
+      }
+      double *p = mom + 3 * i;
+      const double ke0 = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) / rho[i];
+      for (int c = 0; c < 3; ++c) p[c] *= 1.0 - f;
+      const double ke1 = 0.5 * (p[0] * p[0] + p[1] * p[1] + p[2] * p[2]) / rho[i];
+      etot[i] -= ke0 - ke1;
+    } else if (kind[m] == 2) {
+      double v[3];
+      for (int c = 0; c < 3; ++c) v[c] = mom[3 * i + c] / rho[i];
+      const double gam = 1.0 / sqrt(1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (c_light * c_light));
+      for (int k = 0; k < K; ++k) {
+        const double nd = dirs[3 * k] * d[0] + dirs[3 * k + 1] * d[1] + dirs[3 * k + 2] * d[2];
+        if (!(nd >= cos_open[m])) continue;
+        const double vn = v[0] * dirs[3 * k] + v[1] * dirs[3 * k + 1] + v[2] * dirs[3 * k + 2];
+        const double G = gam * (1.0 - vn / c_light);
+        const double G2 = G * G, G4 = G2 * G2;
+        const double x = dt * G * c_red * rho[i] * kP[i];
+        const double Icom = (G4 * Ii[k] + x * S) / (1.0 + x);
+        Ii[k] = Icom / G4;
+      }
+    }
+  }
+}
+#endif
