@@ -62,10 +62,17 @@ enum {
   RT_MESH_ADJOINT = 2  /* one [N][K_max] adjoint buffer for rt_step_adjoint */
 };
 
+/* Kinds of marked cells (rt_marked_upload). */
+enum {
+  RT_CELL_BOUNDARY = 1, /* relaxation to a boundary state (section 2.4) */
+  RT_CELL_EMITTER = 2   /* comoving emission at a radiation temperature (section 2.5) */
+};
+
 #define RT_K_MAX 128
 #define RT_NDIAG 10
 
 typedef struct rt_mesh rt_mesh;
+typedef struct rt_marked rt_marked;
 
 /* Physical and numerical parameters of one call. */
 typedef struct {
@@ -244,6 +251,42 @@ int rt_step_adjoint(rt_mesh *mesh, const rt_params *params, const rt_angles *ang
  */
 int rt_flux_loss(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I,
                  const double *face_weight, double *loss, void *seed, void *stream);
+
+/*
+ * Upload a set of marked cells: boundary cells (section 2.4) and radiation
+ * emitters (section 2.5), applied by rt_marked_apply after each step.  HOST
+ * arrays, n entries (n >= 0; the cells distinct, 0 <= cell < n_cells):
+ *   cell[n]       cell index in a mesh of n_cells cells
+ *   kind[n]       RT_CELL_BOUNDARY or RT_CELL_EMITTER
+ *   T_eff[n]      radiation temperature (>= 0); S = a T_eff^4 / 4 pi
+ *   dir[n][3]     unit direction; the cell's directions of interest are the
+ *                 angles with n_k . dir >= cos_open
+ *   cos_open[n]   opening cosine (> 1 selects no direction)
+ *   tau           relaxation time of boundary cells (> 0)
+ * All arguments are validated on the host before any device memory is
+ * allocated: RT_EINVAL names the first bad entry.  RT_ENOMEM, RT_EHIP.
+ * Synchronises `stream`.
+ */
+int rt_marked_upload(rt_marked **out, int64_t n_cells, int64_t n, const int32_t *cell, const int32_t *kind,
+                     const double *T_eff, const double *dir, const double *cos_open, double tau, void *stream);
+
+/* Release a set of marked cells (NULL is accepted).  Synchronises the device. */
+int rt_marked_free(rt_marked *set);
+
+/*
+ * Apply the marked cells over params->dt, in place, on `stream` (never
+ * allocates).  Boundary cells, with f = min(dt/tau, 1): I_k <- I_k - (I_k - I0_k) f
+ * where I0_k = S in the directions of interest and 0 otherwise (absorbing), and
+ * rho v <- rho v (1 - f) with the kinetic energy that goes with it taken from the
+ * total gas energy (the density is not evolved by the radiation step).  Emitter
+ * cells, in the directions of interest only: the comoving emission-absorption
+ * term at T_eff integrated implicitly, I~' = (I~ + x S)/(1 + x) with
+ * I~ = Gamma^4 I, Gamma = gamma (1 - v.n/c), x = dt Gamma cbar rho kP; the gas is
+ * not changed.  I [N][K] (device, dtype), rho, kP [N] and mom [N][3], etot [N]
+ * (device, FP64).  RT_EINVAL if the set was uploaded for another cell count.
+ */
+int rt_marked_apply(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const rt_marked *set,
+                    void *I, const double *rho, double *mom, double *etot, const double *kP, void *stream);
 
 /*
  * Conservation diagnostics into out[RT_NDIAG] (HOST): sum V E_g,

@@ -2,6 +2,8 @@
 // half-face index every cell gathers through), scratch management and the launch
 // sequence of each call.  All arithmetic of the method runs in the kernels.
 #include <math.h>
+
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -550,6 +552,110 @@ int rt_flux_loss(rt_mesh *m, const rt_params *p, const rt_angles *a, const void 
   hipError_t e = rt_launch_flux_loss(m, a->K, a->dir, a->weight, p->c_light, I, face_weight, loss, seed, p->dtype,
                                      (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "loss kernel launch");
+  return RT_OK;
+}
+
+int rt_marked_free(rt_marked *set) {
+  if (!set) return RT_OK;
+  (void)hipDeviceSynchronize();
+  void *ptrs[] = {set->cell, set->kind, set->T_eff, set->dir, set->cos_open};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  delete set;
+  return RT_OK;
+}
+
+int rt_marked_upload(rt_marked **out, int64_t n_cells, int64_t n, const int32_t *cell, const int32_t *kind,
+                     const double *T_eff, const double *dir, const double *cos_open, double tau, void *stream) {
+  if (!out) return fail(RT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_cells <= 0) return fail(RT_EINVAL, "n_cells=%lld must be positive", (long long)n_cells);
+  if (n < 0 || n > n_cells) return fail(RT_EINVAL, "n=%lld outside [0, n_cells]", (long long)n);
+  if (n > 0 && (!cell || !kind || !T_eff || !dir || !cos_open)) return fail(RT_EINVAL, "a marked-cell array is NULL");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(RT_EINVAL, "tau=%g must be positive and finite", tau);
+  std::vector<uint8_t> seen((size_t)n_cells, 0);
+  for (int64_t m = 0; m < n; ++m) {
+    const int64_t c = cell[m];
+    if (c < 0 || c >= n_cells) return fail(RT_EINVAL, "entry %lld: cell %lld out of range", (long long)m, (long long)c);
+    if (seen[(size_t)c]) return fail(RT_EINVAL, "entry %lld: cell %lld marked twice", (long long)m, (long long)c);
+    seen[(size_t)c] = 1;
+    if (kind[m] != RT_CELL_BOUNDARY && kind[m] != RT_CELL_EMITTER)
+      return fail(RT_EINVAL, "entry %lld: kind %d is neither boundary nor emitter", (long long)m, kind[m]);
+    if (!(T_eff[m] >= 0.0) || !std::isfinite(T_eff[m]))
+      return fail(RT_EINVAL, "entry %lld: T_eff=%g must be finite and >= 0", (long long)m, T_eff[m]);
+    const double *d = dir + 3 * m;
+    const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(fabs(nn - 1.0) <= 1e-12)) return fail(RT_EINVAL, "entry %lld: dir is not a unit vector", (long long)m);
+    if (std::isnan(cos_open[m])) return fail(RT_EINVAL, "entry %lld: cos_open is NaN", (long long)m);
+  }
+  rt_marked *set = new rt_marked;
+  memset(set, 0, sizeof *set);
+  set->n_cells = n_cells;
+  set->n = n;
+  set->tau = tau;
+  hipError_t e = hipSuccess;
+  if (n > 0) {
+    if (e == hipSuccess) e = dmalloc(&set->cell, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = dmalloc(&set->kind, sizeof(int32_t) * n);
+    if (e == hipSuccess) e = dmalloc(&set->T_eff, sizeof(double) * n);
+    if (e == hipSuccess) e = dmalloc(&set->dir, sizeof(double) * 3 * n);
+    if (e == hipSuccess) e = dmalloc(&set->cos_open, sizeof(double) * n);
+    if (e != hipSuccess) {
+      rt_marked_free(set);
+      return fail(RT_ENOMEM, "device allocation of %lld marked cells failed", (long long)n);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const struct {
+      void *dst;
+      const void *src;
+      size_t bytes;
+    } cp[] = {{set->cell, cell, sizeof(int32_t) * n},   {set->kind, kind, sizeof(int32_t) * n},
+              {set->T_eff, T_eff, sizeof(double) * n}, {set->dir, dir, sizeof(double) * 3 * n},
+              {set->cos_open, cos_open, sizeof(double) * n}};
+    for (const auto &c : cp)
+      if (e == hipSuccess) e = hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      rt_marked_free(set);
+      return hip_fail(e, "marked-cell upload");
+    }
+  }
+  *out = set;
+  return RT_OK;
+}
+
+int rt_marked_apply(rt_mesh *m, const rt_params *p, const rt_angles *a, const rt_marked *set, void *I,
+                    const double *rho, double *mom, double *etot, const double *kP, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (!set) return fail(RT_EINVAL, "marked-cell set is NULL");
+  if (set->n_cells != m->N)
+    return fail(RT_EINVAL, "marked cells were uploaded for %lld cells, the mesh has %lld", (long long)set->n_cells,
+                (long long)m->N);
+  if ((rc = check_ptrs({I, rho, mom, etot, kP}))) return rc;
+  rt_marked_args g;
+  memset(&g, 0, sizeof g);
+  g.n = set->n;
+  g.K = a->K;
+  g.cell = set->cell;
+  g.kind = set->kind;
+  g.T_eff = set->T_eff;
+  g.dir = set->dir;
+  g.cos_open = set->cos_open;
+  g.dirs = a->dir;
+  g.W = a->weight;
+  g.I = I;
+  g.rho = rho;
+  g.mom = mom;
+  g.etot = etot;
+  g.kP = kP;
+  g.f = p->dt / set->tau < 1.0 ? p->dt / set->tau : 1.0;
+  g.dt = p->dt;
+  g.a_rad = p->a_rad;
+  g.c_red = p->c_red;
+  g.c_light = p->c_light;
+  hipError_t e = rt_launch_marked(g, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "marked-cell kernel launch");
   return RT_OK;
 }
 

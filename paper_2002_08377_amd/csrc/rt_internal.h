@@ -140,6 +140,35 @@ struct rt_adj_args {
 };
 hipError_t rt_launch_adjoint(const rt_adj_args &a, int dtype, hipStream_t s);
 
+// Marked cells (boundary / emitter) resident on the device.
+struct rt_marked {
+  int64_t n_cells;  // cell count of the mesh the set was made for
+  int64_t n;        // marked cells
+  int32_t *cell, *kind;
+  double *T_eff, *dir, *cos_open;
+  double tau;
+};
+
+struct rt_marked_args {
+  int64_t n;
+  int K;
+  const int32_t *cell;
+  const int32_t *kind;
+  const double *T_eff;
+  const double *dir;
+  const double *cos_open;
+  const double *dirs;
+  const double *W;
+  void *I;
+  const double *rho;
+  double *mom;
+  double *etot;
+  const double *kP;
+  double f;  // min(dt / tau, 1)
+  double dt, a_rad, c_red, c_light;
+};
+hipError_t rt_launch_marked(const rt_marked_args &a, int dtype, hipStream_t s);
+
 hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
                                const void *I, const double *face_weight, double *loss, void *seed, int dtype,
                                hipStream_t s);

@@ -44,6 +44,7 @@ class _Angles(ctypes.Structure):
                 ("weight", ctypes.c_void_p)]
 
 
+CELL_BOUNDARY, CELL_EMITTER = 1, 2
 ANGLES_GENERAL, ANGLES_ANTIPODAL = 0, 1
 
 
@@ -64,6 +65,10 @@ _SIGS = {
     "rt_flux_loss": [ctypes.c_void_p] * 8,
     "rt_diagnostics": [ctypes.c_void_p] * 9,
     "rt_angles_layout": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "rt_marked_upload": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 5
+                        + [ctypes.c_double, ctypes.c_void_p],
+    "rt_marked_free": [ctypes.c_void_p],
+    "rt_marked_apply": [ctypes.c_void_p] * 10,
 }
 
 
@@ -203,6 +208,50 @@ class Mesh:
         _check("rt_mesh_geometry", lib().rt_mesh_geometry(self.ptr, ctypes.c_void_p(wn.data_ptr()),
                                                            ctypes.c_void_p(D.data_ptr()), _stream(stream)))
         return wn, D
+
+
+class MarkedCells:
+    """Boundary and emitter cells uploaded to the library (owns the rt_marked)."""
+
+    def __init__(self, n_cells, cells, kinds, T_eff, direction, cos_open, tau, stream=None):
+        L = lib()
+        arrs = dict(cell=_host(cells, np.int32), kind=_host(kinds, np.int32), T=_host(T_eff, np.float64),
+                    d=_host(direction, np.float64), co=_host(cos_open, np.float64))
+        n = arrs["cell"].shape[0]
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+        ptr = ctypes.c_void_p()
+        rc = L.rt_marked_upload(ctypes.byref(ptr), int(n_cells), n, p(arrs["cell"]), p(arrs["kind"]), p(arrs["T"]),
+                                p(arrs["d"]), p(arrs["co"]), float(tau), _stream(stream))
+        _check("rt_marked_upload", rc)
+        self._ptr = ptr
+        self.n, self.n_cells = n, int(n_cells)
+
+    @property
+    def ptr(self):
+        if self._ptr is None:
+            raise RuntimeError("marked cells were freed")
+        return self._ptr
+
+    def free(self):
+        if getattr(self, "_ptr", None) is not None and _lib is not None:
+            _lib.rt_marked_free(self._ptr)
+        self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def marked_apply(mesh, params, angles, marked, I, rho, mom, etot, kP, stream=None):
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    f = torch.float64
+    rc = lib().rt_marked_apply(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), marked.ptr,
+                               _dev(I, td, (N, K), "I"), _dev(rho, f, (N,), "rho"), _dev(mom, f, (N, 3), "mom"),
+                               _dev(etot, f, (N,), "etot"), _dev(kP, f, (N,), "kP"), _stream(stream))
+    _check("rt_marked_apply", rc)
 
 
 def make_params(c_red, c_light, a_rad, cv, dt, dtype=F64, scheme=UPWIND1) -> Params:

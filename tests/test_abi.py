@@ -85,3 +85,38 @@ def test_angle_layout_detection():
     L = rt.lib()
     out = ctypes.c_int32()
     assert L.rt_angles_layout(0, None, None, ctypes.byref(out)) == rt.RT_EINVAL
+
+
+def test_marked_upload_validates_on_the_host():
+    """Every rejection happens before any device call (this test needs no GPU)."""
+    L = rt.lib()
+    out = ctypes.c_void_p()
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    cell = np.array([0, 3], dtype=np.int32)
+    kind = np.array([rt.CELL_BOUNDARY, rt.CELL_EMITTER], dtype=np.int32)
+    T = np.array([1.0, 2.0])
+    d = np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 0.0]])
+    co = np.array([0.9, 0.5])
+
+    def up(n_cells=10, cell=cell, kind=kind, T=T, d=d, co=co, tau=0.1):
+        rc = L.rt_marked_upload(ctypes.byref(out), n_cells, cell.shape[0], p(cell), p(kind), p(T), p(d), p(co),
+                                tau, None)
+        return rc, L.rt_last_error()
+
+    assert up(n_cells=3)[0] == rt.RT_EINVAL                       # n > n_cells
+    rc, msg = up(n_cells=4, cell=np.array([0, 4], dtype=np.int32))
+    assert rc == rt.RT_EINVAL and b"out of range" in msg
+    rc, msg = up(cell=np.array([3, 3], dtype=np.int32))
+    assert rc == rt.RT_EINVAL and b"marked twice" in msg
+    rc, msg = up(kind=np.array([1, 7], dtype=np.int32))
+    assert rc == rt.RT_EINVAL and b"kind" in msg
+    rc, msg = up(T=np.array([1.0, -1.0]))
+    assert rc == rt.RT_EINVAL and b"T_eff" in msg
+    rc, msg = up(d=np.array([[0.0, 1.0, 0.0], [1.0, 1.0, 0.0]]))
+    assert rc == rt.RT_EINVAL and b"unit" in msg
+    rc, msg = up(co=np.array([0.9, np.nan]))
+    assert rc == rt.RT_EINVAL and b"NaN" in msg
+    rc, msg = up(tau=0.0)
+    assert rc == rt.RT_EINVAL and b"tau" in msg
+    assert out.value is None
+    assert L.rt_marked_free(None) == rt.RT_OK
