@@ -74,6 +74,7 @@ def _load():
             "or_transport_upwind_vjp": [MP, P, INT, P, D, D, P, P, P, P],
             "or_source_vjp": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P, P, P, P, P],
             "or_marked_cells": [I64, P, P, P, P, P, D, INT, P, D, D, D, D, P, P, P, P, P],
+            "or_source_mg": [I64, INT, INT, P, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -364,3 +365,18 @@ def marked_cells(dirs, phys, dt, st: OState, rho, kP, cells, kinds, T_eff, direc
                             phys.a_rad, float(dt), _p(out.I), _p(_f64(rho)), _p(out.mom), _p(out.etot),
                             _p(_f64(kP)))
     return out
+
+
+def source_mg(dirs, W, Wg, phys, dt, I, rho, mom, etot, kP, kJ, ks):
+    """Multigroup source update (section 2.3 generalised to groups coupled through T^4 only).
+
+    I [G][N][K], kP/kJ/ks [G][N], Wg [G]; returns (I', mom', etot', T^{n+1})."""
+    I = _f64(I).copy()
+    G, N, K = I.shape
+    mom = _f64(mom).copy()
+    etot = _f64(etot).copy()
+    T = np.zeros(N)
+    _load().or_source_mg(N, K, G, _p(_f64(dirs)), _p(_f64(W)), _p(_f64(Wg)), phys.c_red, phys.c_light, phys.a_rad,
+                         phys.cv, float(dt), _p(I), _p(_f64(rho)), _p(mom), _p(etot), _p(_f64(kP)), _p(_f64(kJ)),
+                         _p(_f64(ks)), _p(T))
+    return I, mom, etot, T

@@ -733,3 +733,100 @@ void or_marked_cells(int64_t n, const int32_t *cell, const int32_t *kind, const 
   }
 }
 #endif
+
+#ifndef OR_COMPLEX
+/*
+ * Multigroup source update (section 2.3, the implicit form generalised to
+ * frequency groups): groups j = 0..G-1 with weights Wg[j], intensities
+ * I[j][N][K] (group-major), opacities kP[j][N], kJ[j][N], ks[j][N].  Groups couple
+ * only through (T^{n+1})^4.  Per group, as in the grey update: r_kj =
+ * 1/(1 + y chi_j Gamma_k), S1_j, SG_j, SI_j, D_j = S1_j + y kJ_j SG_j and
+ * J~_j = (SI_j + y kP_j SG_j a T^4/4pi) / D_j.  Summing the gas energy equation
+ * over the groups with their weights gives again A T^4 + B T - C = 0 with
+ *   A = dt c rho a sum_j Wg_j kP_j S1_j / D_j,
+ *   C = rho cv T^n + dt c rho 4 pi sum_j Wg_j kJ_j SI_j / D_j,
+ * solved as in the grey case.  The gas receives (c/cbar) sum_j Wg_j (E_j^n - E_j^{n+1})
+ * and sum_j Wg_j (F_j^n - F_j^{n+1}) / (c cbar).  (READING: the emission of group j is
+ * kP_j a T^4/4pi as printed, so a Planck split over groups is carried by kP_j; the
+ * group weights enter the moments and the gas equation as printed.)
+ */
+void or_source_mg(int64_t N, int K, int G, const double *dirs, const double *W, const double *Wg, double c_red,
+                  double c_light, double a_rad, double cv, double dt, double *I, const double *rho, double *mom,
+                  double *etot, const double *kP, const double *kJ, const double *ks, double *T_out) {
+  const double fourpi = 4.0 * OR_PI;
+#pragma omp parallel
+  {
+    double *Gam = (double *)malloc(sizeof(double) * (size_t)K);
+    double *Wt = (double *)malloc(sizeof(double) * (size_t)K);
+    double *S1 = (double *)malloc(sizeof(double) * (size_t)G);
+    double *SG = (double *)malloc(sizeof(double) * (size_t)G);
+    double *SI = (double *)malloc(sizeof(double) * (size_t)G);
+    double *D = (double *)malloc(sizeof(double) * (size_t)G);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      double *p = mom + 3 * i;
+      double v[3];
+      for (int c = 0; c < 3; ++c) v[c] = p[c] / rho[i];
+      const double gam = 1.0 / sqrt(1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (c_light * c_light));
+      double norm = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double vn = v[0] * dirs[3 * k] + v[1] * dirs[3 * k + 1] + v[2] * dirs[3 * k + 2];
+        Gam[k] = gam * (1.0 - vn / c_light);
+        Wt[k] = W[k] / (Gam[k] * Gam[k]);
+        norm += Wt[k];
+      }
+      for (int k = 0; k < K; ++k) Wt[k] /= norm;
+      const double y = dt * c_red * rho[i];
+      /* lab moments before the update, and the comoving sums of every group */
+      double E0 = 0.0, F0[3] = {0.0, 0.0, 0.0};
+      double A = 0.0, Cs = 0.0;
+      for (int j = 0; j < G; ++j) {
+        const double *Ij = I + ((int64_t)j * N + i) * K;
+        const double kPj = kP[(int64_t)j * N + i], kJj = kJ[(int64_t)j * N + i], ksj = ks[(int64_t)j * N + i];
+        const double chi = kJj + ksj;
+        S1[j] = SG[j] = SI[j] = 0.0;
+        for (int k = 0; k < K; ++k) {
+          E0 += Wg[j] * fourpi * W[k] * Ij[k];
+          for (int c = 0; c < 3; ++c) F0[c] += Wg[j] * fourpi * c_light * W[k] * dirs[3 * k + c] * Ij[k];
+          const double G2 = Gam[k] * Gam[k];
+          const double den = 1.0 + y * chi * Gam[k];
+          S1[j] += Wt[k] / den;
+          SG[j] += Wt[k] * Gam[k] / den;
+          SI[j] += Wt[k] * G2 * G2 * Ij[k] / den;
+        }
+        D[j] = S1[j] + y * kJj * SG[j];
+        A += Wg[j] * kPj * S1[j] / D[j];
+        Cs += Wg[j] * kJj * SI[j] / D[j];
+      }
+      const double v2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+      const double Tn = (etot[i] - 0.5 * v2 / rho[i]) / (rho[i] * cv);
+      const double Aq = dt * c_light * rho[i] * a_rad * A;
+      const double Bq = rho[i] * cv;
+      const double Cq = rho[i] * cv * Tn + dt * c_light * rho[i] * fourpi * Cs;
+      const double T = quartic_root(Aq, Bq, Cq);
+      const double T4 = T * T * T * T;
+      const double planck = a_rad * T4 / fourpi;
+      /* per group and angle: the implicit update, boosted back; the new moments */
+      double E1 = 0.0, F1[3] = {0.0, 0.0, 0.0};
+      for (int j = 0; j < G; ++j) {
+        double *Ij = I + ((int64_t)j * N + i) * K;
+        const double kPj = kP[(int64_t)j * N + i], kJj = kJ[(int64_t)j * N + i], ksj = ks[(int64_t)j * N + i];
+        const double chi = kJj + ksj;
+        const double Jc = (SI[j] + y * kPj * SG[j] * planck) / D[j];
+        for (int k = 0; k < K; ++k) {
+          const double G2 = Gam[k] * Gam[k];
+          const double Icom = G2 * G2 * Ij[k];
+          const double Inew = (Icom + y * Gam[k] * (kPj * planck + ksj * Jc)) / (1.0 + y * chi * Gam[k]);
+          Ij[k] = Inew / (G2 * G2);
+          E1 += Wg[j] * fourpi * W[k] * Ij[k];
+          for (int c = 0; c < 3; ++c) F1[c] += Wg[j] * fourpi * c_light * W[k] * dirs[3 * k + c] * Ij[k];
+        }
+      }
+      etot[i] += (c_light / c_red) * (E0 - E1);
+      for (int c = 0; c < 3; ++c) p[c] += (F0[c] - F1[c]) / (c_light * c_red);
+      if (T_out) T_out[i] = T;
+    }
+    free(Gam); free(Wt); free(S1); free(SG); free(SI); free(D);
+  }
+}
+#endif
