@@ -253,6 +253,35 @@ int rt_flux_loss(rt_mesh *mesh, const rt_params *params, const rt_angles *angles
                  const double *face_weight, double *loss, void *seed, void *stream);
 
 /*
+ * Multigroup implicit source update over params->dt (section 2.3, frequency
+ * groups coupled only through the gas temperature), in place.  G groups
+ * (1 <= G <= 16) of K angles each: I [G][N][K] (device, dtype, group-major),
+ * kP, kJ, ks [G][N] (device), group_weight [G] (device): group j enters the
+ * moments and the gas energy and momentum equations with weight Wg_j.  Per
+ * group the comoving sums and J~_j are those of rt_source_implicit; the
+ * temperature solves A T^4 + B T - C = 0 with
+ *   A = dt c rho a sum_j Wg_j kP_j S1_j / D_j,
+ *   C = rho cv T^n + 4 pi dt c rho sum_j Wg_j kJ_j SI_j / D_j.
+ * The emission of group j is kP_j a T^4 / 4pi, so a Planck split over groups is
+ * carried by kP_j.  rho, mom, etot, T_new as in rt_source_implicit.
+ */
+int rt_source_implicit_mg(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, int32_t G,
+                          const double *group_weight, void *I, const double *rho, double *mom, double *etot,
+                          const double *kP, const double *kJ, const double *ks, double *T_new, void *stream);
+
+/*
+ * One multigroup RT_UPWIND1 step: every group's [N][K] slab of I_in is
+ * transported (section 2.2) into I_out, the volumes advance once, then
+ * rt_source_implicit_mg runs on I_out.  Arguments as rt_step and
+ * rt_source_implicit_mg; I_in and I_out ([G][N][K]) must not overlap.
+ * RT_EINVAL for RT_PLM_VL2.
+ */
+int rt_step_mg(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, int32_t G,
+               const double *group_weight, const void *I_in, void *I_out, double *vol, const double *rho,
+               double *mom, double *etot, const double *kP, const double *kJ, const double *ks, double *T_new,
+               void *stream);
+
+/*
  * Upload a set of marked cells: boundary cells (section 2.4) and radiation
  * emitters (section 2.5), applied by rt_marked_apply after each step.  HOST
  * arrays, n entries (n >= 0; the cells distinct, 0 <= cell < n_cells):

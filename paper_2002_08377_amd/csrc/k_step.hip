@@ -239,7 +239,7 @@ template <typename T, int LPC, int APL> hipError_t launch(const rt_step_args &a,
 }
 
 template <typename T> hipError_t dispatch_paired(const rt_step_args &a, hipStream_t s) {
-  switch (rt_step_lanes(a.K, 1)) {
+  switch (rt_paired_lanes(a.K)) {  // 0 (no paired layout for K) matches no case
     case 0x0802: return launch_mode<T, 8, 2, true, true>(a, s);
     case 0x0804: return launch_mode<T, 8, 4, true, true>(a, s);
     case 0x0806: return launch_mode<T, 8, 6, true, true>(a, s);

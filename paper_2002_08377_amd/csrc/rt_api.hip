@@ -555,6 +555,71 @@ int rt_flux_loss(rt_mesh *m, const rt_params *p, const rt_angles *a, const void 
   return RT_OK;
 }
 
+int rt_source_implicit_mg(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t G, const double *group_weight,
+                          void *I, const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
+                          const double *ks, double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (G < 1 || G > RT_G_MAX) return fail(RT_EINVAL, "G=%d outside [1, %d]", G, RT_G_MAX);
+  if ((rc = check_ptrs({group_weight, I, rho, mom, etot, kP, kJ, ks}))) return rc;
+  rt_mg_args g;
+  memset(&g, 0, sizeof g);
+  g.N = m->N;
+  g.K = a->K;
+  g.G = G;
+  g.paired = a->layout == RT_ANGLES_ANTIPODAL;
+  g.dirs = a->dir;
+  g.W = a->weight;
+  g.Wg = group_weight;
+  g.I = I;
+  g.rho = rho;
+  g.mom = mom;
+  g.etot = etot;
+  g.kP = kP;
+  g.kJ = kJ;
+  g.ks = ks;
+  g.T_out = T_new;
+  g.c_red = p->c_red;
+  g.c_light = p->c_light;
+  g.a_rad = p->a_rad;
+  g.cv = p->cv;
+  g.dt = p->dt;
+  g.inv_c = 1.0 / p->c_light;
+  g.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
+  g.m_gain = 4.0 * M_PI / p->c_red;
+  g.a_4pi = p->a_rad / (4.0 * M_PI);
+  hipError_t e = rt_launch_source_mg(g, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "multigroup source kernel launch");
+  return RT_OK;
+}
+
+int rt_step_mg(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t G, const double *group_weight,
+               const void *I_in, void *I_out, double *vol, const double *rho, double *mom, double *etot,
+               const double *kP, const double *kJ, const double *ks, double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "multigroup steps cover RT_UPWIND1 only");
+  if (G < 1 || G > RT_G_MAX) return fail(RT_EINVAL, "G=%d outside [1, %d]", G, RT_G_MAX);
+  if ((rc = check_ptrs({group_weight, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
+  const size_t slab = elem(p->dtype) * m->N * a->K;
+  if (overlap(I_in, I_out, slab * G)) return fail(RT_EINVAL, "I_in and I_out overlap");
+  hipStream_t st = (hipStream_t)stream;
+  // every group's slab is transported by the upwind kernel; the volume advances once
+  for (int32_t j = 0; j < G; ++j) {
+    rt_step_args s = base_args(m, p, a);
+    s.I_in = (const char *)I_in + slab * j;
+    s.I_out = (char *)I_out + slab * j;
+    s.vol_in = vol;
+    s.vol_out = j == G - 1 ? vol : nullptr;
+    s.do_transport = 1;
+    s.do_source = 0;
+    s.write_gas = 0;
+    hipError_t e = rt_launch_step(s, p->dtype, st);
+    if (e != hipSuccess) return hip_fail(e, "multigroup transport kernel launch");
+  }
+  return rt_source_implicit_mg(m, p, a, G, group_weight, I_out, rho, mom, etot, kP, kJ, ks, T_new, stream);
+}
+
 int rt_marked_free(rt_marked *set) {
   if (!set) return RT_OK;
   (void)hipDeviceSynchronize();

@@ -100,12 +100,18 @@ hipError_t rt_launch_volume_rate(rt_mesh *m, hipStream_t s);
 // Lane layout of the step kernel for K angles: (lanes per cell << 8) | angles per lane.
 // Antipodal sets with K/2 a multiple of 8 (K/8 in 2..12) or of 4 (K/4 in {2, 6, 10}) use
 // the paired kernel; everything else 16 lanes (K a multiple of 16 or above 64) or 8.
-static inline int rt_step_lanes(int K, int paired) {
-  if (paired && K % 2 == 0) {
+// The paired layout for K, or 0 when the paired kernel has none (the general kernel
+// then serves the set even if it is antipodal).
+static inline int rt_paired_lanes(int K) {
+  if (K % 2 == 0) {
     const int half = K / 2;
     if (half % 8 == 0 && K / 8 >= 2 && K / 8 <= 12) return (8 << 8) | (K / 8);
     if (half % 4 == 0 && (K / 4 == 2 || K / 4 == 6 || K / 4 == 10)) return (4 << 8) | (K / 4);
   }
+  return 0;
+}
+static inline int rt_step_lanes(int K, int paired) {
+  if (paired && rt_paired_lanes(K)) return rt_paired_lanes(K);
   if (K % 16 == 0 || K > 64) return (16 << 8) | ((K + 15) / 16);
   return (8 << 8) | ((K + 7) / 8);
 }
@@ -139,6 +145,26 @@ struct rt_adj_args {
   double c_red, c_light, a_rad, cv, dt;
 };
 hipError_t rt_launch_adjoint(const rt_adj_args &a, int dtype, hipStream_t s);
+
+// Multigroup source (group-major intensities [G][N][K], opacities [G][N]).
+#define RT_G_MAX 16
+struct rt_mg_args {
+  int64_t N;
+  int K, G;
+  int paired;
+  const double *dirs;
+  const double *W;
+  const double *Wg;  // [G] group weights
+  void *I;
+  const double *rho;
+  double *mom;
+  double *etot;
+  const double *kP, *kJ, *ks;
+  double *T_out;
+  double c_red, c_light, a_rad, cv, dt;
+  double inv_c, e_gain, m_gain, a_4pi;
+};
+hipError_t rt_launch_source_mg(const rt_mg_args &a, int dtype, hipStream_t s);
 
 // Marked cells (boundary / emitter) resident on the device.
 struct rt_marked {

@@ -68,6 +68,8 @@ _SIGS = {
     "rt_marked_upload": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 5
                         + [ctypes.c_double, ctypes.c_void_p],
     "rt_marked_free": [ctypes.c_void_p],
+    "rt_source_implicit_mg": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 10,
+    "rt_step_mg": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 12,
     "rt_marked_apply": [ctypes.c_void_p] * 10,
 }
 
@@ -252,6 +254,39 @@ def marked_apply(mesh, params, angles, marked, I, rho, mom, etot, kP, stream=Non
                                _dev(I, td, (N, K), "I"), _dev(rho, f, (N,), "rho"), _dev(mom, f, (N, 3), "mom"),
                                _dev(etot, f, (N,), "etot"), _dev(kP, f, (N,), "kP"), _stream(stream))
     _check("rt_marked_apply", rc)
+
+
+def _gas_mg(mesh, G, group_weight, rho, mom, etot, kP, kJ, ks):
+    N = mesh.n_cells
+    f = torch.float64
+    return (_dev(group_weight, f, (G,), "group_weight"), _dev(rho, f, (N,), "rho"), _dev(mom, f, (N, 3), "mom"),
+            _dev(etot, f, (N,), "etot"), _dev(kP, f, (G, N), "kP"), _dev(kJ, f, (G, N), "kJ"),
+            _dev(ks, f, (G, N), "ks"))
+
+
+def source_implicit_mg(mesh, params, angles, group_weight, I, rho, mom, etot, kP, kJ, ks, T_new=None, stream=None):
+    """Multigroup source: I [G, N, K] (group-major), kP/kJ/ks [G, N], group_weight [G]."""
+    N, K = _shapes(mesh, angles)
+    G = int(I.shape[0])
+    td = torch_dtype(params.dtype)
+    wg, rho_, mom_, etot_, kP_, kJ_, ks_ = _gas_mg(mesh, G, group_weight, rho, mom, etot, kP, kJ, ks)
+    rc = lib().rt_source_implicit_mg(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), G, wg,
+                                     _dev(I, td, (G, N, K), "I"), rho_, mom_, etot_, kP_, kJ_, ks_,
+                                     _dev(T_new, torch.float64, (N,), "T_new", True), _stream(stream))
+    _check("rt_source_implicit_mg", rc)
+
+
+def step_mg(mesh, params, angles, group_weight, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new=None,
+            stream=None):
+    N, K = _shapes(mesh, angles)
+    G = int(I_in.shape[0])
+    td = torch_dtype(params.dtype)
+    wg, rho_, mom_, etot_, kP_, kJ_, ks_ = _gas_mg(mesh, G, group_weight, rho, mom, etot, kP, kJ, ks)
+    rc = lib().rt_step_mg(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), G, wg,
+                          _dev(I_in, td, (G, N, K), "I_in"), _dev(I_out, td, (G, N, K), "I_out"),
+                          _dev(vol, torch.float64, (N,), "vol"), rho_, mom_, etot_, kP_, kJ_, ks_,
+                          _dev(T_new, torch.float64, (N,), "T_new", True), _stream(stream))
+    _check("rt_step_mg", rc)
 
 
 def make_params(c_red, c_light, a_rad, cv, dt, dtype=F64, scheme=UPWIND1) -> Params:

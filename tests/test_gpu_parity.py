@@ -301,3 +301,21 @@ def test_plm_64c_80a_100_steps_energy_drift():
     e0, e1 = d0[0] + d0[1], d1[0] + d1[1]
     assert abs(e1 - e0) <= 1e-10 * e0
     assert d1[9] == 0 and d1[8] > 0
+
+
+def test_antipodal_set_without_paired_layout_uses_general_kernel():
+    """K = 12 antipodal directions (6 and their opposites): the paired kernel has no layout
+    for K = 12, so the general kernel must serve it; one step matches the oracle."""
+    p = inp.make_problem(0, n=7, K=24, steps=1)
+    rng = np.random.default_rng(4)
+    half = rng.normal(size=(6, 3))
+    half /= np.linalg.norm(half, axis=1, keepdims=True)
+    p.dirs = np.ascontiguousarray(np.concatenate([half, -half]))
+    p.weights = np.full(12, 1.0 / 12)
+    p.state.I = np.ascontiguousarray(p.state.I[:, :12])
+    assert rt.angles_layout(p.dirs, p.weights) == rt.ANGLES_ANTIPODAL
+    dp = DeviceProblem(p)
+    dp.run_gpu(1)
+    so, To = dp.run_oracle(1)
+    assert rel_err(dp.host(dp.I), so.I) < 1e-12
+    assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
