@@ -75,6 +75,7 @@ def _load():
             "or_source_vjp": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P, P, P, P, P],
             "or_marked_cells": [I64, P, P, P, P, P, D, INT, P, D, D, D, D, P, P, P, P, P],
             "or_source_mg": [I64, INT, INT, P, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P],
+            "or_source_kT": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, D, D, D, P],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -379,4 +380,19 @@ def source_mg(dirs, W, Wg, phys, dt, I, rho, mom, etot, kP, kJ, ks):
     _load().or_source_mg(N, K, G, _p(_f64(dirs)), _p(_f64(W)), _p(_f64(Wg)), phys.c_red, phys.c_light, phys.a_rad,
                          phys.cv, float(dt), _p(I), _p(_f64(rho)), _p(mom), _p(etot), _p(_f64(kP)), _p(_f64(kJ)),
                          _p(_f64(ks)), _p(T))
+    return I, mom, etot, T
+
+
+def source_kT(dirs, W, phys, dt, I, rho, mom, etot, kP0, kJ0, ks, T_ref, bP, bJ):
+    """Source update with power-law opacities kX(T) = kX0 (T/T_ref)^bX at T^{n+1} (Newton on T).
+
+    Returns (I', mom', etot', T^{n+1})."""
+    I = _f64(I).copy()
+    N, K = I.shape
+    mom = _f64(mom).copy()
+    etot = _f64(etot).copy()
+    T = np.zeros(N)
+    _load().or_source_kT(N, K, _p(_f64(dirs)), _p(_f64(W)), phys.c_red, phys.c_light, phys.a_rad, phys.cv,
+                         float(dt), _p(I), _p(_f64(rho)), _p(mom), _p(etot), _p(_f64(kP0)), _p(_f64(kJ0)),
+                         _p(_f64(ks)), float(T_ref), float(bP), float(bJ), _p(T))
     return I, mom, etot, T

@@ -830,3 +830,146 @@ void or_source_mg(int64_t N, int K, int G, const double *dirs, const double *W, 
   }
 }
 #endif
+
+#ifndef OR_COMPLEX
+/*
+ * Source update with temperature-dependent opacities (section 2.3: the temperature
+ * equation solved by Newton-Raphson iteration).  READING: the opacities follow power
+ * laws, kP(T) = kP0 (T/T_ref)^bP and kJ(T) = kJ0 (T/T_ref)^bJ, evaluated at
+ * T^{n+1} (the implicit time level of eqs. 27-32); ks is constant.  With J~
+ * eliminated as in the grey update the temperature equation is
+ *   f(T) = rho cv (T - T^n) + dt c rho [kP a T^4 S1 - 4 pi kJ SI] / D = 0,
+ * where S1, SG, SI and D = S1 + y kJ SG depend on T through chi = kJ(T) + ks
+ * (r_k = 1/(1 + y chi Gamma_k)); f' follows from dS/dchi = -y sum W~ Gamma r^2 (.)
+ * and dk/dT = b k / T.  f is negative as T -> 0 and grows like rho cv T, but it
+ * need not be monotone, so plain Newton can fail (READING: the paper names the
+ * method, not its safeguards).  The root is first bracketed from T^n (doubling
+ * upward while f < 0, halving downward while f > 0), then Newton steps are taken
+ * inside the bracket, a bisection replacing any step that leaves it, until a step
+ * changes T by at most 1e-14 T (at most 200 evaluations in all).  The comoving
+ * sums are then evaluated at the final T, and the per-angle update and the
+ * bookkeeping are those of the grey update with the opacities at T^{n+1}.
+ */
+typedef struct {
+  double kP, kJ, S1, SG, SI, D, f, fp;
+} kT_eval;
+
+static kT_eval kT_evaluate(double T, int K, const double *Gam, const double *Wt, const double *Icom, double y,
+                           double rho, double cv, double Tn, double dt, double c_light, double a_rad, double kP0,
+                           double kJ0, double ks, double T_ref, double bP, double bJ) {
+  kT_eval e;
+  e.kP = kP0 * pow(T / T_ref, bP);
+  e.kJ = kJ0 * pow(T / T_ref, bJ);
+  const double chi = e.kJ + ks;
+  double S1p = 0, SGp = 0, SIp = 0;
+  e.S1 = e.SG = e.SI = 0;
+  for (int k = 0; k < K; ++k) {
+    const double r = 1.0 / (1.0 + y * chi * Gam[k]);
+    e.S1 += Wt[k] * r;
+    e.SG += Wt[k] * Gam[k] * r;
+    e.SI += Wt[k] * Icom[k] * r;
+    S1p += Wt[k] * Gam[k] * r * r;
+    SGp += Wt[k] * Gam[k] * Gam[k] * r * r;
+    SIp += Wt[k] * Icom[k] * Gam[k] * r * r;
+  }
+  e.D = e.S1 + y * e.kJ * e.SG;
+  const double fourpi = 4.0 * OR_PI;
+  const double T3 = T * T * T, T4 = T3 * T;
+  const double Nn = e.kP * a_rad * T4 * e.S1 - fourpi * e.kJ * e.SI;
+  e.f = rho * cv * (T - Tn) + dt * c_light * rho * Nn / e.D;
+  const double dkP = bP * e.kP / T, dkJ = bJ * e.kJ / T;
+  const double dS1 = -y * S1p * dkJ, dSG = -y * SGp * dkJ, dSI = -y * SIp * dkJ;
+  const double dD = dS1 + y * (dkJ * e.SG + e.kJ * dSG);
+  const double dN = dkP * a_rad * T4 * e.S1 + e.kP * a_rad * 4.0 * T3 * e.S1 + e.kP * a_rad * T4 * dS1 -
+                    fourpi * (dkJ * e.SI + e.kJ * dSI);
+  e.fp = rho * cv + dt * c_light * rho * (dN * e.D - Nn * dD) / (e.D * e.D);
+  return e;
+}
+
+void or_source_kT(int64_t N, int K, const double *dirs, const double *W, double c_red, double c_light,
+                  double a_rad, double cv, double dt, double *I, const double *rho, double *mom, double *etot,
+                  const double *kP0, const double *kJ0, const double *ks, double T_ref, double bP, double bJ,
+                  double *T_out) {
+  const double fourpi = 4.0 * OR_PI;
+#pragma omp parallel
+  {
+    double *Gam = (double *)malloc(sizeof(double) * (size_t)K);
+    double *Wt = (double *)malloc(sizeof(double) * (size_t)K);
+    double *Icom = (double *)malloc(sizeof(double) * (size_t)K);
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+      double *Ii = I + i * K;
+      double *p = mom + 3 * i;
+      double E0 = 0.0, F0[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < K; ++k) {
+        E0 += fourpi * W[k] * Ii[k];
+        for (int c = 0; c < 3; ++c) F0[c] += fourpi * c_light * W[k] * dirs[3 * k + c] * Ii[k];
+      }
+      double v[3];
+      for (int c = 0; c < 3; ++c) v[c] = p[c] / rho[i];
+      const double gam = 1.0 / sqrt(1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (c_light * c_light));
+      double norm = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double vn = v[0] * dirs[3 * k] + v[1] * dirs[3 * k + 1] + v[2] * dirs[3 * k + 2];
+        Gam[k] = gam * (1.0 - vn / c_light);
+        const double G2 = Gam[k] * Gam[k];
+        Icom[k] = G2 * G2 * Ii[k];
+        Wt[k] = W[k] / G2;
+        norm += Wt[k];
+      }
+      for (int k = 0; k < K; ++k) Wt[k] /= norm;
+      const double y = dt * c_red * rho[i];
+      const double v2 = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+      const double Tn = (etot[i] - 0.5 * v2 / rho[i]) / (rho[i] * cv);
+#define KT_EVAL(T) kT_evaluate((T), K, Gam, Wt, Icom, y, rho[i], cv, Tn, dt, c_light, a_rad, kP0[i], kJ0[i], ks[i], \
+                               T_ref, bP, bJ)
+      /* bracket the root from T^n */
+      double T = Tn, lo = Tn, hi = Tn;
+      kT_eval e = KT_EVAL(T);
+      int nev = 1;
+      if (e.f < 0.0) {
+        for (kT_eval eh = e; eh.f < 0.0 && nev < 200; ++nev) {
+          lo = hi;
+          hi *= 2.0;
+          eh = KT_EVAL(hi);
+        }
+      } else if (e.f > 0.0) {
+        for (kT_eval el = e; el.f > 0.0 && nev < 200; ++nev) {
+          hi = lo;
+          lo *= 0.5;
+          el = KT_EVAL(lo);
+        }
+      }
+      /* safeguarded Newton from T^n inside [lo, hi] */
+      while (e.f != 0.0 && nev < 200) {
+        if (e.f < 0.0) lo = T;
+        else hi = T;
+        double Tq = T - e.f / e.fp;
+        if (!(Tq > lo && Tq < hi)) Tq = 0.5 * (lo + hi);
+        const int done = fabs(Tq - T) <= 1e-14 * T;
+        T = Tq;
+        e = KT_EVAL(T);
+        ++nev;
+        if (done) break;
+      }
+#undef KT_EVAL
+      const double T4 = T * T * T * T;
+      const double planck = a_rad * T4 / fourpi;
+      const double Jc = (e.SI + y * e.kP * e.SG * planck) / e.D;
+      const double chi = e.kJ + ks[i];
+      double E1 = 0.0, F1[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < K; ++k) {
+        const double Inew = (Icom[k] + y * Gam[k] * (e.kP * planck + ks[i] * Jc)) / (1.0 + y * chi * Gam[k]);
+        const double G2 = Gam[k] * Gam[k];
+        Ii[k] = Inew / (G2 * G2);
+        E1 += fourpi * W[k] * Ii[k];
+        for (int c = 0; c < 3; ++c) F1[c] += fourpi * c_light * W[k] * dirs[3 * k + c] * Ii[k];
+      }
+      etot[i] += (c_light / c_red) * (E0 - E1);
+      for (int c = 0; c < 3; ++c) p[c] += (F0[c] - F1[c]) / (c_light * c_red);
+      if (T_out) T_out[i] = T;
+    }
+    free(Gam); free(Wt); free(Icom);
+  }
+}
+#endif
