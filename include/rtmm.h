@@ -282,6 +282,34 @@ int rt_step_mg(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, 
                void *stream);
 
 /*
+ * Implicit source update with temperature-dependent opacities over params->dt
+ * (section 2.3, where the temperature equation is solved by Newton-Raphson
+ * iteration), in place on I [N][K].  Power laws at T^{n+1}:
+ * kP(T) = kP0 (T/T_ref)^bP, kJ(T) = kJ0 (T/T_ref)^bJ (kP0, kJ0 [N] device;
+ * T_ref > 0; |bP|, |bJ| <= 20); ks [N] is constant.  With J~ eliminated the
+ * temperature equation is f(T) = rho cv (T - T^n) + dt c rho [kP a T^4 S1 -
+ * 4 pi kJ SI] / D = 0, whose comoving sums depend on T through kJ.  The root is
+ * bracketed from T^n (doubling up while f < 0, halving down while f > 0) and
+ * found by Newton steps kept inside the bracket (bisection otherwise) to a step
+ * of at most 1e-14 T.  Where f has several roots this gives the one reached from
+ * T^n.  With bP = bJ = 0 it gives the root of rt_source_implicit's quartic.
+ * Per-angle arithmetic is FP64 in both precision forms.  Other arguments as
+ * rt_source_implicit.
+ */
+int rt_source_implicit_kT(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, void *I,
+                          const double *rho, double *mom, double *etot, const double *kP0, const double *kJ0,
+                          const double *ks, double T_ref, double bP, double bJ, double *T_new, void *stream);
+
+/*
+ * One RT_UPWIND1 step with temperature-dependent opacities: upwind transport
+ * (as rt_transport_step) into I_out, then rt_source_implicit_kT on I_out.
+ * Arguments as rt_step and rt_source_implicit_kT.  RT_EINVAL for RT_PLM_VL2.
+ */
+int rt_step_kT(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_in, void *I_out,
+               double *vol, const double *rho, double *mom, double *etot, const double *kP0, const double *kJ0,
+               const double *ks, double T_ref, double bP, double bJ, double *T_new, void *stream);
+
+/*
  * Upload a set of marked cells: boundary cells (section 2.4) and radiation
  * emitters (section 2.5), applied by rt_marked_apply after each step.  HOST
  * arrays, n entries (n >= 0; the cells distinct, 0 <= cell < n_cells):

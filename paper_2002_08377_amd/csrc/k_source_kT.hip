@@ -1,0 +1,190 @@
+// Implicit source update with temperature-dependent opacities (section 2.3: the
+// temperature equation solved by Newton-Raphson iteration), one cell per group of LPC
+// lanes.  kP(T) = kP0 (T/T_ref)^bP, kJ(T) = kJ0 (T/T_ref)^bJ at T^{n+1}; ks constant.
+// With J~ eliminated the temperature equation is
+//   f(T) = rho cv (T - T^n) + dt c rho [kP a T^4 S1 - 4 pi kJ SI] / D,
+// whose comoving sums depend on T through chi = kJ(T) + ks; every evaluation sums the
+// angles again (S1, SG, SI and their chi-derivatives) and reduces over the lanes, so
+// all lanes of a cell take the same steps.  The root is bracketed from T^n (doubling
+// upward while f < 0, halving downward while f > 0), then found by Newton steps kept
+// inside the bracket (bisection when a step leaves it) until a step changes T by at most
+// 1e-14 T; at most 200 evaluations.  Per-angle arithmetic is FP64 in both precision
+// forms; the update and the bookkeeping are those of the grey source.
+#include "rt_step_common.h"
+
+namespace {
+
+struct kT_eval {
+  double kP, kJ, S1, SG, SI, D, f, fp;
+};
+
+template <typename T, int LPC, int APL, bool FULL, bool PAIRED>
+__global__ __launch_bounds__(RT_BLOCK) void k_source_kT(rt_kT_args a, int64_t nblk) {
+  using Ang = rt_step_angles<double, LPC, APL, FULL, PAIRED>;
+  constexpr int CPB = RT_BLOCK / LPC;
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  const int64_t cell = lb * CPB + threadIdx.x / LPC;
+  if (cell >= a.N) return;
+  const int l = threadIdx.x % LPC;
+  const int K = a.K;
+  Ang ang;
+  ang.load(a.dirs, a.W, K, l);
+  T *Ir = (T *)a.I + cell * (int64_t)K;
+
+  const double rho = a.rho[cell];
+  const double m0 = a.mom[3 * cell], m1 = a.mom[3 * cell + 1], m2 = a.mom[3 * cell + 2];
+  const double Eg = a.etot[cell];
+  const double c = a.c_light, fourpi = 4.0 * RT_PI;
+  const double vx = m0 / rho, vy = m1 / rho, vz = m2 / rho;
+  const double gam = 1.0 / sqrt(1.0 - (vx * vx + vy * vy + vz * vz) / (c * c));
+  double Gm[APL], Wt[APL], Ic[APL], I0[APL];
+  double norm = 0.0;
+#pragma unroll
+  for (int q = 0; q < APL; ++q) {
+    I0[q] = (double)Ir[ang.k[q]];
+    const double vn = vx * ang.dx(q) + vy * ang.dy(q) + vz * ang.dz(q);
+    Gm[q] = gam * (1.0 - vn / c);
+    const double G2 = Gm[q] * Gm[q];
+    Ic[q] = G2 * G2 * I0[q];
+    Wt[q] = ang.wt(q) / G2;
+    norm += Wt[q];
+  }
+  norm = rt_group_sum<LPC>(norm);
+#pragma unroll
+  for (int q = 0; q < APL; ++q) Wt[q] /= norm;
+  const double y = a.dt * a.c_red * rho;
+  const double rcv = rho * a.cv;
+  const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rcv;
+  const double kP0 = a.kP0[cell], kJ0 = a.kJ0[cell], ks = a.ks[cell];
+
+  auto evaluate = [&](double Tq) {
+    kT_eval e;
+    e.kP = kP0 * pow(Tq / a.T_ref, a.bP);
+    e.kJ = kJ0 * pow(Tq / a.T_ref, a.bJ);
+    const double chi = e.kJ + ks;
+    double s1 = 0, sG = 0, sI = 0, p1 = 0, pG = 0, pI = 0;
+#pragma unroll
+    for (int q = 0; q < APL; ++q) {
+      const double r = 1.0 / (1.0 + y * chi * Gm[q]);
+      s1 += Wt[q] * r;
+      sG += Wt[q] * Gm[q] * r;
+      sI += Wt[q] * Ic[q] * r;
+      p1 += Wt[q] * Gm[q] * r * r;
+      pG += Wt[q] * Gm[q] * Gm[q] * r * r;
+      pI += Wt[q] * Ic[q] * Gm[q] * r * r;
+    }
+    e.S1 = rt_group_sum<LPC>(s1);
+    e.SG = rt_group_sum<LPC>(sG);
+    e.SI = rt_group_sum<LPC>(sI);
+    p1 = rt_group_sum<LPC>(p1);
+    pG = rt_group_sum<LPC>(pG);
+    pI = rt_group_sum<LPC>(pI);
+    e.D = e.S1 + y * e.kJ * e.SG;
+    const double T3 = Tq * Tq * Tq, T4 = T3 * Tq;
+    const double Nn = e.kP * a.a_rad * T4 * e.S1 - fourpi * e.kJ * e.SI;
+    e.f = rcv * (Tq - Tn) + a.dt * c * rho * Nn / e.D;
+    const double dkP = a.bP * e.kP / Tq, dkJ = a.bJ * e.kJ / Tq;
+    const double dS1 = -y * p1 * dkJ, dSG = -y * pG * dkJ, dSI = -y * pI * dkJ;
+    const double dD = dS1 + y * (dkJ * e.SG + e.kJ * dSG);
+    const double dN = dkP * a.a_rad * T4 * e.S1 + e.kP * a.a_rad * 4.0 * T3 * e.S1 + e.kP * a.a_rad * T4 * dS1 -
+                      fourpi * (dkJ * e.SI + e.kJ * dSI);
+    e.fp = rcv + a.dt * c * rho * (dN * e.D - Nn * dD) / (e.D * e.D);
+    return e;
+  };
+
+  // bracket the root from T^n, then safeguarded Newton inside the bracket
+  double Tq = Tn, lo = Tn, hi = Tn;
+  kT_eval e = evaluate(Tq);
+  int nev = 1;
+  if (e.f < 0.0) {
+    for (kT_eval eh = e; eh.f < 0.0 && nev < 200; ++nev) {
+      lo = hi;
+      hi *= 2.0;
+      eh = evaluate(hi);
+    }
+  } else if (e.f > 0.0) {
+    for (kT_eval el = e; el.f > 0.0 && nev < 200; ++nev) {
+      hi = lo;
+      lo *= 0.5;
+      el = evaluate(lo);
+    }
+  }
+  while (e.f != 0.0 && nev < 200) {
+    if (e.f < 0.0) lo = Tq;
+    else hi = Tq;
+    double Tx = Tq - e.f / e.fp;
+    if (!(Tx > lo && Tx < hi)) Tx = 0.5 * (lo + hi);
+    const bool done = fabs(Tx - Tq) <= 1e-14 * Tq;
+    Tq = Tx;
+    e = evaluate(Tq);
+    ++nev;
+    if (done) break;
+  }
+
+  const double T4 = Tq * Tq * Tq * Tq;
+  const double planck = a.a_rad * T4 / fourpi;
+  const double Jc = (e.SI + y * e.kP * e.SG * planck) / e.D;
+  const double chi = e.kJ + ks;
+  double dE = 0, dFx = 0, dFy = 0, dFz = 0;
+#pragma unroll
+  for (int q = 0; q < APL; ++q) {
+    const double Inew = (Ic[q] + y * Gm[q] * (e.kP * planck + ks * Jc)) / (1.0 + y * chi * Gm[q]);
+    const double G2 = Gm[q] * Gm[q];
+    const T out = (T)(Inew / (G2 * G2));
+    if (ang.ok[q]) Ir[ang.k[q]] = out;
+    const double wd = ang.wt(q) * (I0[q] - (double)out);
+    dE += wd;
+    dFx += wd * ang.dx(q);
+    dFy += wd * ang.dy(q);
+    dFz += wd * ang.dz(q);
+  }
+  dE = rt_group_sum<LPC>(dE);
+  dFx = rt_group_sum<LPC>(dFx);
+  dFy = rt_group_sum<LPC>(dFy);
+  dFz = rt_group_sum<LPC>(dFz);
+  if (l == 0) {
+    a.etot[cell] = Eg + a.e_gain * dE;
+    a.mom[3 * cell] = m0 + a.m_gain * dFx;
+    a.mom[3 * cell + 1] = m1 + a.m_gain * dFy;
+    a.mom[3 * cell + 2] = m2 + a.m_gain * dFz;
+    if (a.T_out) a.T_out[cell] = Tq;
+  }
+}
+
+template <typename T, int LPC, int APL, bool FULL, bool PAIRED>
+hipError_t launch(const rt_kT_args &a, hipStream_t s) {
+  const int64_t cpb = RT_BLOCK / LPC;
+  const int64_t nblk = (a.N + cpb - 1) / cpb;
+  hipLaunchKernelGGL((k_source_kT<T, LPC, APL, FULL, PAIRED>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK),
+                     0, s, a, nblk);
+  return hipGetLastError();
+}
+
+template <typename T> hipError_t dispatch(const rt_kT_args &a, hipStream_t s) {
+  switch (rt_step_lanes(a.K, 0)) {
+    case 0x1001: return launch<T, 16, 1, false, false>(a, s);
+    case 0x1002: return launch<T, 16, 2, false, false>(a, s);
+    case 0x1003: return launch<T, 16, 3, false, false>(a, s);
+    case 0x1004: return launch<T, 16, 4, false, false>(a, s);
+    case 0x1005: return launch<T, 16, 5, false, false>(a, s);
+    case 0x1006: return launch<T, 16, 6, false, false>(a, s);
+    case 0x1007: return launch<T, 16, 7, false, false>(a, s);
+    case 0x1008: return launch<T, 16, 8, false, false>(a, s);
+    case 0x0801: return launch<T, 8, 1, false, false>(a, s);
+    case 0x0802: return launch<T, 8, 2, false, false>(a, s);
+    case 0x0803: return launch<T, 8, 3, false, false>(a, s);
+    case 0x0804: return launch<T, 8, 4, false, false>(a, s);
+    case 0x0805: return launch<T, 8, 5, false, false>(a, s);
+    case 0x0806: return launch<T, 8, 6, false, false>(a, s);
+    case 0x0807: return launch<T, 8, 7, false, false>(a, s);
+    case 0x0808: return launch<T, 8, 8, false, false>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t rt_launch_source_kT(const rt_kT_args &a, int dtype, hipStream_t s) {
+  return dtype == RT_F32 ? dispatch<float>(a, s) : dispatch<double>(a, s);
+}

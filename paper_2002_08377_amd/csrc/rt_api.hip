@@ -620,6 +620,57 @@ int rt_step_mg(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t G, co
   return rt_source_implicit_mg(m, p, a, G, group_weight, I_out, rho, mom, etot, kP, kJ, ks, T_new, stream);
 }
 
+int rt_source_implicit_kT(rt_mesh *m, const rt_params *p, const rt_angles *a, void *I, const double *rho,
+                          double *mom, double *etot, const double *kP0, const double *kJ0, const double *ks,
+                          double T_ref, double bP, double bJ, double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (!(T_ref > 0.0) || !std::isfinite(T_ref)) return fail(RT_EINVAL, "T_ref=%g must be positive and finite", T_ref);
+  if (!(fabs(bP) <= 20.0) || !(fabs(bJ) <= 20.0))
+    return fail(RT_EINVAL, "opacity exponents (%g, %g) outside [-20, 20]", bP, bJ);
+  if ((rc = check_ptrs({I, rho, mom, etot, kP0, kJ0, ks}))) return rc;
+  rt_kT_args g;
+  memset(&g, 0, sizeof g);
+  g.N = m->N;
+  g.K = a->K;
+  g.dirs = a->dir;
+  g.W = a->weight;
+  g.I = I;
+  g.rho = rho;
+  g.mom = mom;
+  g.etot = etot;
+  g.kP0 = kP0;
+  g.kJ0 = kJ0;
+  g.ks = ks;
+  g.T_out = T_new;
+  g.T_ref = T_ref;
+  g.bP = bP;
+  g.bJ = bJ;
+  g.c_red = p->c_red;
+  g.c_light = p->c_light;
+  g.a_rad = p->a_rad;
+  g.cv = p->cv;
+  g.dt = p->dt;
+  g.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
+  g.m_gain = 4.0 * M_PI / p->c_red;
+  hipError_t e = rt_launch_source_kT(g, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "temperature-dependent-opacity source kernel launch");
+  return RT_OK;
+}
+
+int rt_step_kT(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, double *vol,
+               const double *rho, double *mom, double *etot, const double *kP0, const double *kJ0, const double *ks,
+               double T_ref, double bP, double bJ, double *T_new, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "steps with T-dependent opacities cover RT_UPWIND1 only");
+  if ((rc = check_ptrs({I_in, I_out, vol}))) return rc;
+  if (overlap(I_in, I_out, elem(p->dtype) * m->N * a->K)) return fail(RT_EINVAL, "I_in and I_out overlap");
+  if ((rc = run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP0, kJ0, ks, nullptr, false, (hipStream_t)stream)))
+    return rc;
+  return rt_source_implicit_kT(m, p, a, I_out, rho, mom, etot, kP0, kJ0, ks, T_ref, bP, bJ, T_new, stream);
+}
+
 int rt_marked_free(rt_marked *set) {
   if (!set) return RT_OK;
   (void)hipDeviceSynchronize();

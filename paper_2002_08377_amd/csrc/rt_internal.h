@@ -166,6 +166,24 @@ struct rt_mg_args {
 };
 hipError_t rt_launch_source_mg(const rt_mg_args &a, int dtype, hipStream_t s);
 
+// Source with power-law temperature-dependent opacities.
+struct rt_kT_args {
+  int64_t N;
+  int K;
+  const double *dirs;
+  const double *W;
+  void *I;
+  const double *rho;
+  double *mom;
+  double *etot;
+  const double *kP0, *kJ0, *ks;
+  double *T_out;
+  double T_ref, bP, bJ;
+  double c_red, c_light, a_rad, cv, dt;
+  double e_gain, m_gain;
+};
+hipError_t rt_launch_source_kT(const rt_kT_args &a, int dtype, hipStream_t s);
+
 // Marked cells (boundary / emitter) resident on the device.
 struct rt_marked {
   int64_t n_cells;  // cell count of the mesh the set was made for

@@ -69,6 +69,8 @@ _SIGS = {
                         + [ctypes.c_double, ctypes.c_void_p],
     "rt_marked_free": [ctypes.c_void_p],
     "rt_source_implicit_mg": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 10,
+    "rt_source_implicit_kT": [ctypes.c_void_p] * 10 + [ctypes.c_double] * 3 + [ctypes.c_void_p] * 2,
+    "rt_step_kT": [ctypes.c_void_p] * 12 + [ctypes.c_double] * 3 + [ctypes.c_void_p] * 2,
     "rt_step_mg": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 12,
     "rt_marked_apply": [ctypes.c_void_p] * 10,
 }
@@ -254,6 +256,28 @@ def marked_apply(mesh, params, angles, marked, I, rho, mom, etot, kP, stream=Non
                                _dev(I, td, (N, K), "I"), _dev(rho, f, (N,), "rho"), _dev(mom, f, (N, 3), "mom"),
                                _dev(etot, f, (N,), "etot"), _dev(kP, f, (N,), "kP"), _stream(stream))
     _check("rt_marked_apply", rc)
+
+
+def source_implicit_kT(mesh, params, angles, I, rho, mom, etot, kP0, kJ0, ks, T_ref, bP, bJ, T_new=None,
+                       stream=None):
+    """Source with power-law opacities kX(T) = kX0 (T/T_ref)^bX at T^{n+1}."""
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    rc = lib().rt_source_implicit_kT(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), _dev(I, td, (N, K), "I"),
+                                     *_gas(mesh, rho, mom, etot, kP0, kJ0, ks), float(T_ref), float(bP), float(bJ),
+                                     _dev(T_new, torch.float64, (N,), "T_new", True), _stream(stream))
+    _check("rt_source_implicit_kT", rc)
+
+
+def step_kT(mesh, params, angles, I_in, I_out, vol, rho, mom, etot, kP0, kJ0, ks, T_ref, bP, bJ, T_new=None,
+            stream=None):
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    rc = lib().rt_step_kT(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), _dev(I_in, td, (N, K), "I_in"),
+                          _dev(I_out, td, (N, K), "I_out"), _dev(vol, torch.float64, (N,), "vol"),
+                          *_gas(mesh, rho, mom, etot, kP0, kJ0, ks), float(T_ref), float(bP), float(bJ),
+                          _dev(T_new, torch.float64, (N,), "T_new", True), _stream(stream))
+    _check("rt_step_kT", rc)
 
 
 def _gas_mg(mesh, G, group_weight, rho, mom, etot, kP, kJ, ks):
