@@ -27,16 +27,44 @@ __device__ __forceinline__ int64_t rt_logical_block(int64_t nblk) {
 
 static inline int64_t rt_grid_for(int64_t nblk) { return ((nblk + 7) / 8) * 8; }
 
-// Sum over the LPC lanes of a cell group.  The xor butterfly leaves bit-identical
-// totals in every lane of the group (each pairwise add is commutative).
+// A double from another lane of the same row of 16 by a DPP lane permutation (both
+// halves moved by v_mov_dpp; no LDS round trip).  Controls used below (gfx9 encodings):
+// quad_perm [1,0,3,2] = lane ^ 1, quad_perm [2,3,0,1] = lane ^ 2, row_half_mirror =
+// lane 7 - i within each 8, row_mirror = lane 15 - i within each 16.
+template <int CTRL> __device__ __forceinline__ double rt_dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the LPC lanes of a cell group (groups are aligned runs of LPC lanes, all
+// active).  Each step adds the value of a partner lane whose own step adds this lane's
+// value (pairs by lane ^ 1, lane ^ 2, then the mirrored quad and half-row), so every
+// lane of the group ends with the bit-identical total (each pairwise add is
+// commutative).  Groups wider than 16 lanes use the xor butterfly through LDS.
 template <int LPC> __device__ __forceinline__ double rt_group_sum(double v) {
+  if constexpr (LPC <= 16) {
+    if constexpr (LPC >= 2) v += rt_dpp<0xB1>(v);
+    if constexpr (LPC >= 4) v += rt_dpp<0x4E>(v);
+    if constexpr (LPC >= 8) v += rt_dpp<0x141>(v);
+    if constexpr (LPC >= 16) v += rt_dpp<0x140>(v);
+  } else {
 #pragma unroll
-  for (int o = LPC / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPC);
+    for (int o = LPC / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LPC);
+  }
   return v;
 }
 template <int LPC> __device__ __forceinline__ double rt_group_min(double v) {
+  if constexpr (LPC <= 16) {
+    if constexpr (LPC >= 2) v = fmin(v, rt_dpp<0xB1>(v));
+    if constexpr (LPC >= 4) v = fmin(v, rt_dpp<0x4E>(v));
+    if constexpr (LPC >= 8) v = fmin(v, rt_dpp<0x141>(v));
+    if constexpr (LPC >= 16) v = fmin(v, rt_dpp<0x140>(v));
+  } else {
 #pragma unroll
-  for (int o = LPC / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, LPC));
+    for (int o = LPC / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, LPC));
+  }
   return v;
 }
 
