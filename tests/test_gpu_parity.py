@@ -166,6 +166,45 @@ def test_plm_64c_80a_one_step(dtype):
         assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
 
 
+@pytest.fixture(scope="module")
+def throughput_problem():
+    """The throughput workload at full size (128^3 cells, 80 angles) and one oracle step of it."""
+    p = inp.make_problem(3, steps=1)
+    st = p.state
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    so, To = orc.run(om, p.dirs, p.weights, p.phys, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot), st.rho, st.kP,
+                     st.kJ, st.ks, 1, "upwind1")
+    return p, so, To
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_throughput_128c_80a_one_step(dtype, throughput_problem):
+    """The throughput workload at full size in the launch the bench times (fused step, paired
+    lane layout, 2,097,152 cells x 80 angles): every cell and angle against the oracle."""
+    p, so, To = throughput_problem
+    st = p.state
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=80)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, p.dt, dtype)
+    td = rt.torch_dtype(dtype)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    I = d(st.I).to(td).contiguous()
+    I2 = torch.empty_like(I)
+    vol, mom, etot, T = d(st.vol), d(st.mom), d(st.etot), torch.zeros(st.rho.shape, dtype=torch.float64, device="cuda")
+    rt.step(mesh, prm, ang, I, I2, vol, d(st.rho), mom, etot, d(st.kP), d(st.kJ), d(st.ks), T)
+    torch.cuda.synchronize()
+    err = {"I": rel_err(I2.double().cpu().numpy(), so.I), "T": rel_err(T.cpu().numpy(), To),
+           "etot": rel_err(etot.cpu().numpy(), so.etot), "mom": rel_err(mom.cpu().numpy(), so.mom),
+           "vol": rel_err(vol.cpu().numpy(), so.vol)}
+    print(dtype, err)
+    mesh.free()
+    assert err["I"] < TOL[dtype] and err["vol"] < 1e-14
+    # the FP32 form's gas follows its FP32 transported intensities
+    tol_gas = {"T": 1e-12, "etot": 1e-12, "mom": 1e-12} if dtype == rt.F64 else {"T": 1e-6, "etot": 1e-6, "mom": 1e-6}
+    for k, t in tol_gas.items():
+        assert err[k] < t, (k, err[k])
+
+
 def test_flux_loss_and_seed_match_oracle():
     p = _prob(2, n=10, K=48)
     dp = DeviceProblem(p)
