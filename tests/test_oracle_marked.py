@@ -11,11 +11,16 @@
 * Moving emitter: the comoving equilibrium I = S / Gamma^4 is a fixed point.
 * Directions outside the opening cone, unmarked cells and (for emitters) the gas
   are untouched bit for bit.
+* A beam from an emitter layer past an optically thick sphere (the paper's shadow
+  set-up, section 3.4) leaves a shadow: behind the sphere the radiation energy is
+  below half of that in the lit band at the same height, which itself is far
+  above the faint start.
 """
 import numpy as np
 
 import oracle as orc
 from paper_2002_08377_amd import inputs as inp
+from shadow_setup import radiation_energy, shadow_problem
 
 PHYS = inp.Physics()
 
@@ -99,3 +104,21 @@ def test_moving_emitter_comoving_equilibrium_is_fixed_point():
     out = orc.marked_cells(dirs, PHYS, 0.01, eq, rho, kP, [0], [2], [Te], [d], [c], 1.0)
     np.testing.assert_allclose(out.I[0], eq.I[0], rtol=1e-14)
     assert not np.allclose(G, 1.0)
+
+
+def test_beam_casts_shadow_behind_opaque_sphere():
+    p, mset, reg = shadow_problem(16, 80, 60)
+    st = p.state
+    cells, kinds, T, d, co = mset
+    assert (p.dirs @ d[0] >= co[0]).sum() == 4
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    s = orc.OState(st.I, st.vol, st.mom, st.etot)
+    for _ in range(p.steps):
+        s, _ = orc.step(om, p.dirs, p.weights, p.phys, p.dt, s, st.rho, st.kP, st.kJ, st.ks)
+        s = orc.marked_cells(p.dirs, p.phys, p.dt, s, st.rho, st.kP, cells, kinds, T, d, co, p.dt)
+    E = radiation_energy(s.I, p.weights)
+    E0 = radiation_energy(st.I, p.weights)
+    shadow, lit = E[reg["shadow"]].mean(), E[reg["lit"]].mean()
+    assert reg["shadow"].sum() >= 4 and reg["lit"].sum() >= 100
+    assert lit > 100 * E0[reg["lit"]].mean()
+    assert shadow < 0.5 * lit
