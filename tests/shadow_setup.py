@@ -1,4 +1,4 @@
-"""A beam-and-shadow set-up after the paper's shadow tests (section 3.4), as inputs only.
+"""A beam-and-shadow set-up after the paper's shadow test (section 3.5), as inputs only.
 
 A layer of emitter cells at y = 0.1 beams along +y into the angles within the
 opening cosine of +y (the 4 angles nearest +y of the level-symmetric set); an

@@ -7,7 +7,7 @@
   emitters along z, beaming at 45 and 135 degrees in the x-y plane, an absorbing
   layer at the top in y, near-vacuum elsewhere; 10 full steps (transport,
   source, marked cells) agree with the oracle to 1e-12 (FP64) / 1e-5 (FP32).
-* The shadow set-up (section 3.4): an emitter layer beaming along +y past an
+* The shadow set-up (section 3.5): an emitter layer beaming along +y past an
   optically thick sphere, 24^3 cells, 80 angles, 90 full steps: agrees with the
   oracle to 1e-12 (FP64) / 1e-5 (FP32), and the GPU result shows the shadow
   (behind the sphere below half the lit band's radiation energy).

@@ -12,7 +12,7 @@
 * Directions outside the opening cone, unmarked cells and (for emitters) the gas
   are untouched bit for bit.
 * A beam from an emitter layer past an optically thick sphere (the paper's shadow
-  set-up, section 3.4) leaves a shadow: behind the sphere the radiation energy is
+  set-up, section 3.5) leaves a shadow: behind the sphere the radiation energy is
   below half of that in the lit band at the same height, which itself is far
   above the faint start.
 """
