@@ -3,8 +3,10 @@
 Tolerances (normwise, max|gpu - oracle| / max|oracle|): FP64 path <= 1e-12 on
 intensities, temperatures, gas energy and momentum; FP32-transport path
 <= 1e-5 on intensities.  Sizes span several workgroups with a ragged tail
-(7^3 = 343 cells is not a multiple of the 16 or 32 cells per workgroup) and
-every lane layout of the kernels (K = 8, 20, 24, 48, 80).
+(7^3 = 343 cells is not a multiple of the 16 or 32 cells per workgroup), a
+hand-built 8-cell lattice with doubled face pairs, the full 128^3 x 80
+throughput workload, and every lane layout of the kernels (K = 8, 20, 24, 48,
+80, 120, 128).
 """
 import numpy as np
 import pytest
@@ -219,8 +221,11 @@ def test_flux_loss_and_seed_match_oracle():
     assert rel_err(seed.cpu().numpy() - 0.5, so) < 1e-13
 
 
-def test_adjoint_matches_oracle():
-    p = _prob(2, n=8, K=24, steps=4)
+@pytest.mark.parametrize("K", [24, 80, 120])
+def test_adjoint_matches_oracle(K):
+    """Reverse of 4 steps against the oracle's reverse mode: K = 24 (16 lanes x 2 angles), 80
+    (16 x 5) and 120, the largest level-symmetric set (16 x 8, every lane slot used)."""
+    p = _prob(2, n=8, K=K, steps=4)
     st = p.state
     dp = DeviceProblem(p, flags=rt.MESH_ADJOINT)
     # forward on the GPU, recording the source inputs of every step
@@ -358,3 +363,83 @@ def test_antipodal_set_without_paired_layout_uses_general_kernel():
     so, To = dp.run_oracle(1)
     assert rel_err(dp.host(dp.I), so.I) < 1e-12
     assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
+
+
+def _lattice2_problem(K):
+    """The 2x2x2 periodic cubic lattice (h = 1/2), built by hand: 8 cells, fewer than one
+    workgroup, and every cell meets each of its three axis neighbours through two faces (its
+    +e and -e faces lead to the same cell), a pairing the jittered builder never produces."""
+    n, h, box = 2, 0.5, 1.0
+    lat = np.array([(a, b, c) for c in range(2) for b in range(2) for a in range(2)], dtype=np.int32)
+    gen = (lat + 0.5) * h
+    fc, fs, fn, fcen = [], [], [], []
+    for i, site in enumerate(lat):
+        for ax in range(3):
+            for sgn in (1, -1):
+                nb = site.copy()
+                nb[ax] = (nb[ax] + sgn) % 2
+                j = int(nb[0] + 2 * nb[1] + 4 * nb[2])
+                if j < i:
+                    continue  # listed from the lower cell
+                e = np.zeros(3)
+                e[ax] = sgn
+                fc.append((i, j))
+                fs.append(np.rint((gen[i] + h * e - gen[j]) / box).astype(np.int8))
+                fn.append(e)
+                fcen.append(gen[i] + 0.5 * h * e)
+    F = len(fc)
+    mesh = inp.Mesh(n=n, box=box, gen=gen, com=gen.copy(), vol=np.full(8, h ** 3), cell_lat=lat,
+                    face_cells=np.array(fc, np.int32), face_shift=np.array(fs, np.int8),
+                    face_area=np.full(F, h * h), face_normal=np.array(fn), face_centroid=np.array(fcen))
+    phys = inp.Physics()
+    dirs, w = inp.angle_set(K)
+    st = inp.initial_state(mesh, K, inp.seed_streams(0), phys)
+    return inp.Problem(mesh=mesh, dirs=dirs, weights=w, state=st, phys=phys, dt=inp.courant_dt(mesh, phys.c_red),
+                       steps=3, scheme="upwind1")
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("K", [8, 24, 80])
+def test_two_cubed_lattice_steps_match_oracle(dtype, K):
+    p = _lattice2_problem(K)
+    assert p.mesh.n_faces == 24 and len(set(map(tuple, p.mesh.face_cells))) == 12
+    dp = DeviceProblem(p, dtype=dtype)
+    dp.run_gpu(p.steps)
+    so, To = dp.run_oracle(p.steps)
+    assert rel_err(dp.host(dp.I), so.I) < TOL[dtype]
+    if dtype == rt.F64:
+        assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
+        assert rel_err(dp.etot.cpu().numpy(), so.etot) < 1e-12
+        assert rel_err(dp.mom.cpu().numpy(), so.mom) < 1e-12
+        assert rel_err(dp.vol.cpu().numpy(), so.vol) < 1e-14
+
+
+def _random_angle_problem(K, n=6, seed=3):
+    """K random unit directions with random positive weights (no symmetry: the general lane
+    layout), intensities drawn by the common recipe."""
+    p = _prob(0, n=n, K=24, steps=2)
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(K, 3))
+    p.dirs = np.ascontiguousarray(d / np.linalg.norm(d, axis=1, keepdims=True))
+    w = rng.uniform(0.5, 1.5, K)
+    p.weights = w / w.sum()
+    T = p.state.T
+    p.state.I = np.ascontiguousarray((p.phys.a_rad * T ** 4 / (4 * np.pi))[:, None]
+                                     * (1.0 + 0.1 * rng.normal(size=(T.size, K))))
+    return p
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("K", [120, 128])
+def test_largest_angle_sets_steps_match_oracle(dtype, K):
+    """The largest angle counts: the level-symmetric 120-angle set (antipodal, but with no paired
+    lane layout) and 128 random directions (RT_K_MAX, every lane slot of the general layout)."""
+    p = _prob(0, n=6, K=120, steps=2) if K == 120 else _random_angle_problem(K)
+    dp = DeviceProblem(p, dtype=dtype)
+    dp.run_gpu(p.steps)
+    so, To = dp.run_oracle(p.steps)
+    assert rel_err(dp.host(dp.I), so.I) < TOL[dtype]
+    if dtype == rt.F64:
+        assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
+        assert rel_err(dp.etot.cpu().numpy(), so.etot) < 1e-12
+        assert rel_err(dp.mom.cpu().numpy(), so.mom) < 1e-12
