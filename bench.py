@@ -237,20 +237,46 @@ def counters_summary(pmc_dir, copy_bytes):
     return {"source_hash": kernel_source_hash(), "scale": scale, "kernels": out}
 
 
-def cpu_baseline(prob, steps, log):
-    """The FP64 oracle (plain C, OpenMP) on the host cores: `steps` full steps of the same workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(prob, steps, log, one_thread_steps=1):
+    """The FP64 oracle (plain C, OpenMP) on the host cores: `steps` full steps of the same workload
+    on all its threads, then `one_thread_steps` on one thread."""
     import oracle as orc
     st = prob.state
     om = orc.OracleMesh(prob.mesh, st.mesh_vel)
     s0 = orc.OState(st.I, st.vol, st.mom, st.etot)
+    N, K = st.I.shape
+    threads = orc.num_threads()
     t0 = time.perf_counter()
     orc.run(om, prob.dirs, prob.weights, prob.phys, prob.dt, s0, st.rho, st.kP, st.kJ, st.ks, steps)
     dt = time.perf_counter() - t0
-    N, K = st.I.shape
-    log(f"  oracle: {steps} steps in {dt:.2f} s on {orc.num_threads()} threads")
-    return dict(value=N * K * steps / dt, unit="cell-angle updates/s", cores=orc.num_threads(), kind="oracle",
-                sample=f"{steps} full FP64 first-order steps of the {N}-cell x {K}-angle workload "
-                       f"({dt:.1f} s)")
+    log(f"  oracle: {steps} steps in {dt:.2f} s on {threads} threads")
+    out = dict(value=N * K * steps / dt, unit="cell-angle updates/s", cores=threads, kind="oracle",
+               sample=f"{steps} full FP64 first-order steps of the {N}-cell x {K}-angle workload "
+                      f"({dt:.1f} s)", cpu_model=cpu_model(), nproc=os.cpu_count())
+    if one_thread_steps > 0:
+        orc.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            orc.run(om, prob.dirs, prob.weights, prob.phys, prob.dt, s0, st.rho, st.kP, st.kJ, st.ks,
+                    one_thread_steps)
+            d1 = time.perf_counter() - t0
+        finally:
+            orc.set_num_threads(threads)
+        log(f"  oracle: {one_thread_steps} step(s) in {d1:.2f} s on 1 thread")
+        out["one_thread"] = dict(value=N * K * one_thread_steps / d1, unit="cell-angle updates/s", cores=1,
+                                 sample=f"{one_thread_steps} full step(s) of the same workload ({d1:.1f} s)")
+    return out
 
 
 def main():

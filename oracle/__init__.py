@@ -83,6 +83,8 @@ def _load():
             fn.restype = None
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = INT
+        lib.or_set_num_threads.argtypes = [INT]
+        lib.or_set_num_threads.restype = None
         lib.or_quartic_root.argtypes = [D, D, D]
         lib.or_quartic_root.restype = D
         for name in ("or_flux_loss", "or_flux_loss_cs"):
@@ -227,6 +229,11 @@ def flux_loss(om: OracleMesh, dirs, W, c_light, I, face_weight, want_seed=False,
 def num_threads() -> int:
     """Threads used by the oracle's OpenMP loops."""
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's OpenMP loops from now on (n >= 1)."""
+    _load().or_set_num_threads(int(n))
 
 
 def quartic_root(A, B, C):

@@ -323,6 +323,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads for the OpenMP loops that follow (timing on one core, say); n >= 1. */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* The temperature root alone, exported for the tests. */
 double or_quartic_root(double A, double B, double C) { return quartic_root(A, B, C); }
 #endif
