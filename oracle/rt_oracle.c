@@ -854,8 +854,9 @@ void or_source_mg(int64_t N, int K, int G, const double *dirs, const double *W, 
  * need not be monotone, so plain Newton can fail (READING: the paper names the
  * method, not its safeguards).  The root is first bracketed from T^n (doubling
  * upward while f < 0, halving downward while f > 0), then Newton steps are taken
- * inside the bracket, a bisection replacing any step that leaves it, until a step
- * changes T by at most 1e-14 T (at most 200 evaluations in all).  The comoving
+ * inside the bracket, a bisection replacing any larger step that leaves it, until
+ * a step changes T by at most 1e-14 T; that converged step is taken as it is, even
+ * when rounding puts it on the bracket's end (at most 200 evaluations in all).  The comoving
  * sums are then evaluated at the final T, and the per-angle update and the
  * bookkeeping are those of the grey update with the opacities at T^{n+1}.
  */
@@ -954,8 +955,10 @@ void or_source_kT(int64_t N, int K, const double *dirs, const double *W, double 
         if (e.f < 0.0) lo = T;
         else hi = T;
         double Tq = T - e.f / e.fp;
-        if (!(Tq > lo && Tq < hi)) Tq = 0.5 * (lo + hi);
+        /* a step within the tolerance has converged and is taken as it is; a larger one that
+           leaves the bracket is replaced by bisection */
         const int done = fabs(Tq - T) <= 1e-14 * T;
+        if (!done && !(Tq > lo && Tq < hi)) Tq = 0.5 * (lo + hi);
         T = Tq;
         e = KT_EVAL(T);
         ++nev;
