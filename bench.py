@@ -203,6 +203,120 @@ def run_plm(log):
     return out
 
 
+def _ms_per_call(fn, reps, warmup=2):
+    """Mean time of `reps` calls of fn on the current stream (HIP events around the whole run)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _roofline(ms, nbytes, ops=None):
+    """HBM roofline of `nbytes` algorithmic bytes (and the ALU one of `ops`, if given) in `ms`; the
+    bound whose peak needs more time comes first, the other beside it."""
+    t = ms * 1e-3
+    hbm = {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_per_launch": int(nbytes)}
+    if ops is None:
+        return hbm
+    alu = {"bound": "alu", "achieved": round(ops / t / 1e12, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
+           "frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4), "algorithmic_per_launch": int(ops)}
+    main, other = (alu, hbm) if ops / ALU_PEAK_TOPS / 1e12 > nbytes / HBM_PEAK_GBS / 1e9 else (hbm, alu)
+    out = dict(main)
+    out["other"] = other
+    return out
+
+
+def run_extensions(prob, mesh, angles, log, reps=5):
+    """The extension rows on the throughput mesh (128^3 cells, 80 angles), FP32 transport form:
+    multigroup (4 groups: a step of 4 transports plus the multigroup source, and that source alone),
+    temperature-dependent opacities (Kramers-like power laws, exponent -3.5: the step and its source
+    alone), and boundary/emitter cells (1% of the cells marked: one application).  Each kernel's
+    roofline counts its algorithmic bytes (each value read and written once); the multigroup source
+    also its ~38 operations per cell, angle and group.  The kappa(T) source is bound by FP64
+    arithmetic (each Newton evaluation re-forms the comoving sums over all angles), whose count
+    depends on the cell, so only its HBM fraction is given."""
+    import torch
+    from paper_2002_08377_amd import rt
+    st, ph = prob.state, prob.phys
+    N, K = st.I.shape
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, prob.dt, rt.F32)
+    rho, ks = d(st.rho), d(st.ks)
+    out = {"workload": f"throughput_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "dtype": "f32"}
+
+    # multigroup
+    G = 4
+    wg = d([0.1, 0.2, 0.3, 0.4])
+    scale = np.array([0.3, 1.0, 3.0, 10.0])[:, None]
+    kPg, kJg, ksg = d(scale * st.kP[None, :]), d(scale * st.kJ[None, :]), d(np.tile(st.ks, (G, 1)))
+    Ig = torch.as_tensor(st.I, device="cuda").float().unsqueeze(0).repeat(G, 1, 1).contiguous()
+    Ig2 = torch.empty_like(Ig)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    bufs = [Ig, Ig2]
+
+    def mg_step():
+        rt.step_mg(mesh, prm, angles, wg, bufs[0], bufs[1], vol, rho, mom, etot, kPg, kJg, ksg)
+        bufs.reverse()
+
+    ms_step = _ms_per_call(mg_step, reps)
+    ms_src = _ms_per_call(lambda: rt.source_implicit_mg(mesh, prm, angles, wg, bufs[0], rho, mom, etot, kPg, kJg,
+                                                        ksg), reps)
+    src_bytes = G * N * K * 4 * 2 + N * (72 + 24 * G)
+    out["multigroup"] = {"groups": G, "ms_per_step": round(ms_step, 4),
+                         "value": N * K * G / (ms_step * 1e-3), "unit": "cell-angle-group updates/s",
+                         "source_kernel": "k_source_mg", "source_ms": round(ms_src, 4),
+                         "roofline": _roofline(ms_src, src_bytes, N * K * G * SOURCE_OPS_PER_CA)}
+    log(f"  multigroup ({G} groups): {ms_step:.3f} ms/step, source {ms_src:.3f} ms")
+    del Ig, Ig2, bufs, kPg, kJg, ksg
+
+    # temperature-dependent opacities
+    I = torch.as_tensor(st.I, device="cuda").float().contiguous()
+    I2 = torch.empty_like(I)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    kP0, kJ0 = d(st.kP), d(st.kJ)
+    law = (1.0, -3.5, -3.5)
+    bufs = [I, I2]
+
+    def kT_step():
+        rt.step_kT(mesh, prm, angles, bufs[0], bufs[1], vol, rho, mom, etot, kP0, kJ0, ks, *law)
+        bufs.reverse()
+
+    ms_step = _ms_per_call(kT_step, reps)
+    ms_src = _ms_per_call(lambda: rt.source_implicit_kT(mesh, prm, angles, bufs[0], rho, mom, etot, kP0, kJ0, ks,
+                                                        *law), reps)
+    out["opacity_T"] = {"law": {"T_ref": law[0], "bP": law[1], "bJ": law[2]}, "ms_per_step": round(ms_step, 4),
+                        "value": N * K / (ms_step * 1e-3), "unit": "cell-angle updates/s",
+                        "source_kernel": "k_source_kT", "source_ms": round(ms_src, 4),
+                        "roofline": _roofline(ms_src, N * K * 4 * 2 + N * 96)}
+    log(f"  kappa(T): {ms_step:.3f} ms/step, source {ms_src:.3f} ms")
+
+    # boundary and emitter cells
+    rng = np.random.default_rng(2002)
+    M = N // 100
+    cells = rng.choice(N, M, replace=False)
+    kinds = np.where(np.arange(M) % 2 == 0, rt.CELL_BOUNDARY, rt.CELL_EMITTER)
+    dirs = rng.normal(size=(M, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    mk = rt.MarkedCells(N, cells, kinds, rng.uniform(0.5, 2.0, M), dirs, np.full(M, 0.8), 4.0 * prob.dt)
+    kP = d(st.kP)
+    ms_mk = _ms_per_call(lambda: rt.marked_apply(mesh, prm, angles, mk, bufs[0], rho, mom, etot, kP), reps)
+    mk_bytes = M * (K * 4 * 2 + 8 + 48 + 16 + 8 + 48)
+    out["marked_cells"] = {"marked": M, "ms_per_apply": round(ms_mk, 4), "kernel": "k_marked",
+                           "roofline": _roofline(ms_mk, mk_bytes)}
+    log(f"  marked cells ({M}): {ms_mk:.3f} ms per application")
+    mk.free()
+    return out
+
+
 def counters_summary(pmc_dir, copy_bytes):
     """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch) over a bench run with --copy-calibration; each counter is scaled by what it reads
@@ -292,6 +406,8 @@ def main():
                          "traffic, to scale hardware byte counters)")
     ap.add_argument("--no-fwd-adj", action="store_true", help="skip the forward+adjoint measurement")
     ap.add_argument("--no-plm", action="store_true", help="skip the PLM throughput / energy-drift measurement")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the multigroup / kappa(T) / marked-cell measurements")
     ap.add_argument("--counters-summary", metavar="PMC_DIR",
                     help="write profiles/traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE output and exit")
     ap.add_argument("--quiet", action="store_true")
@@ -304,7 +420,7 @@ def main():
         summ = counters_summary(args.counters_summary, n ** 3 * K * 4)
         summ["command"] = ("rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --kernel-include-regex 'k_step|neg' "
                            "--output-format csv -- python3 bench.py --steps 2 --warmup 1 --cpu-steps 0 "
-                           "--no-fwd-adj --no-plm --copy-calibration")
+                           "--no-fwd-adj --no-plm --no-extensions --copy-calibration")
         with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
             json.dump(summ, f, indent=1)
         print(json.dumps(summ))
@@ -393,6 +509,8 @@ def main():
         "f32_over_f64": res["f64"]["wall"] / res["f32"]["wall"],
         "f32_vs_f64_rel_err_I": err,
     }
+    if not args.no_extensions:
+        out["extensions"] = run_extensions(prob, mesh, angles, log)
     mesh.free()
     if not args.no_fwd_adj:
         out["fwd_adj"] = run_fwd_adj(log)

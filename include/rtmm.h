@@ -291,7 +291,7 @@ int rt_step_mg(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, 
  * 4 pi kJ SI] / D = 0, whose comoving sums depend on T through kJ.  The root is
  * bracketed from T^n (doubling up while f < 0, halving down while f > 0) and
  * found by Newton steps kept inside the bracket (bisection otherwise) to a step
- * of at most 1e-14 T.  Where f has several roots this gives the one reached from
+ * of at most 1e-14 T, which is taken as it is.  Where f has several roots this gives the one reached from
  * T^n.  With bP = bJ = 0 it gives the root of rt_source_implicit's quartic.
  * Per-angle arithmetic is FP64 in both precision forms.  Other arguments as
  * rt_source_implicit.
