@@ -51,12 +51,18 @@ def algorithmic_ops(N, F, K):
     return N * K * SOURCE_OPS_PER_CA + F * K * FACE_OPS_PER_FA
 
 
+# The sources the step kernel is compiled from: its file and every header it includes.
+STEP_KERNEL_SOURCES = ("paper_2002_08377_amd/csrc/k_step.hip", "paper_2002_08377_amd/csrc/rt_step_common.h",
+                       "paper_2002_08377_amd/csrc/rt_device.h", "paper_2002_08377_amd/csrc/rt_internal.h",
+                       "include/rtmm.h")
+
+
 def kernel_source_hash():
+    """Hash of the step kernel's sources: the counter summary is used only while they are unchanged."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2002_08377_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
+    for rel in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode())
             h.update(f.read())
     return h.hexdigest()[:16]
 
