@@ -38,15 +38,15 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_kT(rt_kT_args a, int64_t nb
   const double c = a.c_light, fourpi = 4.0 * RT_PI;
   const double vx = m0 / rho, vy = m1 / rho, vz = m2 / rho;
   const double gam = 1.0 / sqrt(1.0 - (vx * vx + vy * vy + vz * vz) / (c * c));
-  double Gm[APL], Wt[APL], Ic[APL], I0[APL];
+  double Gm[APL], Wt[APL], Ic[APL];
   double norm = 0.0;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    I0[q] = (double)Ir[ang.k[q]];
+    const double I0 = (double)Ir[ang.k[q]];
     const double vn = vx * ang.dx(q) + vy * ang.dy(q) + vz * ang.dz(q);
     Gm[q] = gam * (1.0 - vn / c);
     const double G2 = Gm[q] * Gm[q];
-    Ic[q] = G2 * G2 * I0[q];
+    Ic[q] = G2 * G2 * I0;
     Wt[q] = ang.wt(q) / G2;
     norm += Wt[q];
   }
@@ -95,35 +95,50 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_kT(rt_kT_args a, int64_t nb
     return e;
   };
 
-  // bracket the root from T^n, then safeguarded Newton inside the bracket
-  double Tq = Tn, lo = Tn, hi = Tn;
-  kT_eval e = evaluate(Tq);
-  int nev = 1;
-  if (e.f < 0.0) {
-    for (kT_eval eh = e; eh.f < 0.0 && nev < 200; ++nev) {
+  // Bracket the root from T^n, then safeguarded Newton inside the bracket.  One loop with a
+  // single evaluation site (mode 0: at T^n; 1: doubling hi while f < 0; 2: halving lo while
+  // f > 0; 3: Newton), taking the same steps in the same order as the two bracket loops and
+  // the Newton loop it replaces, so the kernel holds one copy of the evaluation.
+  double Tq = Tn, lo = Tn, hi = Tn, x = Tn;
+  int mode = 0;
+  bool done = false;
+  kT_eval e;
+  for (int nev = 1;; ++nev) {
+    const kT_eval r = evaluate(x);
+    if (mode == 0) {
+      e = r;
+      mode = r.f < 0.0 ? 1 : r.f > 0.0 ? 2 : 3;
+    } else if (mode == 1) {
+      if (!(r.f < 0.0)) mode = 3;
+    } else if (mode == 2) {
+      if (!(r.f > 0.0)) mode = 3;
+    } else {
+      Tq = x;
+      e = r;
+      if (done) break;
+    }
+    if (nev >= 200) break;
+    if (mode == 1) {
       lo = hi;
       hi *= 2.0;
-      eh = evaluate(hi);
+      x = hi;
+      continue;
     }
-  } else if (e.f > 0.0) {
-    for (kT_eval el = e; el.f > 0.0 && nev < 200; ++nev) {
+    if (mode == 2) {
       hi = lo;
       lo *= 0.5;
-      el = evaluate(lo);
+      x = lo;
+      continue;
     }
-  }
-  while (e.f != 0.0 && nev < 200) {
+    if (e.f == 0.0) break;
     if (e.f < 0.0) lo = Tq;
     else hi = Tq;
     double Tx = Tq - e.f / e.fp;
     // a step within the tolerance has converged and is taken as it is; a larger one that
     // leaves the bracket is replaced by bisection
-    const bool done = fabs(Tx - Tq) <= 1e-14 * Tq;
+    done = fabs(Tx - Tq) <= 1e-14 * Tq;
     if (!done && !(Tx > lo && Tx < hi)) Tx = 0.5 * (lo + hi);
-    Tq = Tx;
-    e = evaluate(Tq);
-    ++nev;
-    if (done) break;
+    x = Tx;
   }
 
   const double T4 = Tq * Tq * Tq * Tq;
@@ -136,8 +151,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_kT(rt_kT_args a, int64_t nb
     const double Inew = (Ic[q] + y * Gm[q] * (e.kP * planck + ks * Jc)) / (1.0 + y * chi * Gm[q]);
     const double G2 = Gm[q] * Gm[q];
     const T out = (T)(Inew / (G2 * G2));
+    // the incoming value is read again here rather than held through the iteration
+    const double wd = ang.wt(q) * ((double)Ir[ang.k[q]] - (double)out);
     if (ang.ok[q]) Ir[ang.k[q]] = out;
-    const double wd = ang.wt(q) * (I0[q] - (double)out);
     dE += wd;
     dFx += wd * ang.dx(q);
     dFy += wd * ang.dy(q);
@@ -165,7 +181,22 @@ hipError_t launch(const rt_kT_args &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Antipodal sets with a paired layout put 4 or 8 lanes on a cell (more cells per wave, so the
+// per-cell scalar work of each evaluation is shared by fewer lanes); others the general one.
 template <typename T> hipError_t dispatch(const rt_kT_args &a, hipStream_t s) {
+  if (a.paired) {
+    switch (rt_paired_lanes(a.K)) {
+      case 0x0802: return launch<T, 8, 2, true, true>(a, s);
+      case 0x0804: return launch<T, 8, 4, true, true>(a, s);
+      case 0x0806: return launch<T, 8, 6, true, true>(a, s);
+      case 0x0808: return launch<T, 8, 8, true, true>(a, s);
+      case 0x080a: return launch<T, 8, 10, true, true>(a, s);
+      case 0x080c: return launch<T, 8, 12, true, true>(a, s);
+      case 0x0402: return launch<T, 4, 2, true, true>(a, s);
+      case 0x0406: return launch<T, 4, 6, true, true>(a, s);
+      case 0x040a: return launch<T, 4, 10, true, true>(a, s);
+    }
+  }
   switch (rt_step_lanes(a.K, 0)) {
     case 0x1001: return launch<T, 16, 1, false, false>(a, s);
     case 0x1002: return launch<T, 16, 2, false, false>(a, s);

@@ -653,6 +653,7 @@ int rt_source_implicit_kT(rt_mesh *m, const rt_params *p, const rt_angles *a, vo
   g.dt = p->dt;
   g.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
   g.m_gain = 4.0 * M_PI / p->c_red;
+  g.paired = a->layout == RT_ANGLES_ANTIPODAL;
   hipError_t e = rt_launch_source_kT(g, p->dtype, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "temperature-dependent-opacity source kernel launch");
   return RT_OK;

@@ -181,6 +181,7 @@ struct rt_kT_args {
   double T_ref, bP, bJ;
   double c_red, c_light, a_rad, cv, dt;
   double e_gain, m_gain;
+  int paired;  // angles in the RT_ANGLES_ANTIPODAL layout
 };
 hipError_t rt_launch_source_kT(const rt_kT_args &a, int dtype, hipStream_t s);
 
