@@ -71,6 +71,7 @@ def _load():
             "or_source": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P],
             "or_source_cs": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P],
             "or_diagnostics": [I64, INT, P, P, D, D, P, P, P, P, P],
+            "or_moments": [I64, INT, P, P, D, P, P],
             "or_transport_upwind_vjp": [MP, P, INT, P, D, D, P, P, P, P],
             "or_source_vjp": [I64, INT, P, P, D, D, D, D, D, P, P, P, P, P, P, P, P, P, P, P, P],
             "or_marked_cells": [I64, P, P, P, P, P, D, INT, P, D, D, D, D, P, P, P, P, P],
@@ -239,6 +240,15 @@ def set_num_threads(n: int) -> None:
 def quartic_root(A, B, C):
     """Positive root of A T^4 + B T - C = 0 as the source step solves it."""
     return _load().or_quartic_root(float(A), float(B), float(C))
+
+
+def moments(dirs, W, c_light, I):
+    """Per-cell angle moments [N, 10]: E_r, F_r (3), P_r (xx, yy, zz, xy, xz, yz), section 2.1."""
+    I = _f64(I)
+    N, K = I.shape
+    out = np.empty((N, 10))
+    _load().or_moments(N, K, _p(_f64(dirs)), _p(_f64(W)), float(c_light), _p(I), _p(out))
+    return out
 
 
 def diagnostics(dirs, W, phys, I, vol, etot, mom):

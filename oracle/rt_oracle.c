@@ -465,6 +465,39 @@ void SFX(or_flux_loss)(const or_mesh *m, int K, const double *dirs, const double
 }
 
 /*
+ * Angle moments per cell (section 2.1: the zeroth, first and second moments J, H, K of
+ * the intensity and E_r = 4 pi J / c, F_r = 4 pi H, P_r = 4 pi K / c).  With the
+ * intensities carried as I = I_std / c (energy-density units) they are
+ *   E_r = 4 pi sum_k W_k I_k,  F_r = 4 pi c sum_k W_k n_k I_k,  P_r = 4 pi sum_k W_k n_k n_k I_k.
+ * out[N][10] = (E_r, F_x, F_y, F_z, P_xx, P_yy, P_zz, P_xy, P_xz, P_yz).
+ */
+#ifndef OR_COMPLEX
+void or_moments(int64_t N, int K, const double *dirs, const double *W, double c_light, const double *I,
+                double *out) {
+  const double fourpi = 4.0 * OR_PI;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < K; ++k) {
+      const double wI = W[k] * I[i * K + k];
+      const double *n = dirs + 3 * k;
+      m[0] += wI;
+      for (int c = 0; c < 3; ++c) m[1 + c] += wI * n[c];
+      m[4] += wI * n[0] * n[0];
+      m[5] += wI * n[1] * n[1];
+      m[6] += wI * n[2] * n[2];
+      m[7] += wI * n[0] * n[1];
+      m[8] += wI * n[0] * n[2];
+      m[9] += wI * n[1] * n[2];
+    }
+    out[10 * i] = fourpi * m[0];
+    for (int c = 1; c < 4; ++c) out[10 * i + c] = fourpi * c_light * m[c];
+    for (int c = 4; c < 10; ++c) out[10 * i + c] = fourpi * m[c];
+  }
+}
+#endif
+
+/*
  * Conservation diagnostics (section 2.3.1, eqs. 37-38): out[0] = sum V E_g,
  * out[1] = sum V (c/cbar) E_r, out[2..4] = sum V rho v, out[5..7] =
  * sum V F_r/(c cbar), out[8] = min I, out[9] = number of non-finite values in
