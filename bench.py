@@ -249,7 +249,8 @@ def run_extensions(prob, mesh, angles, log, reps=5):
     """The extension rows on the throughput mesh (128^3 cells, 80 angles), FP32 transport form:
     multigroup (4 groups: a step of 4 transports plus the multigroup source, and that source alone),
     temperature-dependent opacities (Kramers-like power laws, exponent -3.5: the step and its source
-    alone), and boundary/emitter cells (1% of the cells marked: one application).  Each kernel's
+    alone), boundary/emitter cells (1% of the cells marked: one application) and the per-cell
+    angle moments (one read of I, 10 doubles written per cell).  Each kernel's
     roofline counts its algorithmic bytes (each value read and written once); the multigroup source
     also its ~38 operations per cell, angle and group.  The kappa(T) source is bound by FP64
     arithmetic (each Newton evaluation re-forms the comoving sums over all angles), whose count
@@ -324,6 +325,13 @@ def run_extensions(prob, mesh, angles, log, reps=5):
                            "roofline": _roofline(ms_mk, mk_bytes)}
     log(f"  marked cells ({M}): {ms_mk:.3f} ms per application")
     mk.free()
+
+    # per-cell angle moments (E_r, F_r, P_r)
+    mo = torch.empty((N, 10), dtype=torch.float64, device="cuda")
+    ms_mo = _ms_per_call(lambda: rt.moments(mesh, prm, angles, bufs[0], mo), reps)
+    out["moments"] = {"ms": round(ms_mo, 4), "kernel": "k_moments",
+                      "roofline": _roofline(ms_mo, N * K * 4 + N * 80)}
+    log(f"  moments: {ms_mo:.3f} ms")
     return out
 
 

@@ -346,6 +346,19 @@ int rt_marked_apply(rt_mesh *mesh, const rt_params *params, const rt_angles *ang
                     void *I, const double *rho, double *mom, double *etot, const double *kP, void *stream);
 
 /*
+ * Angle moments of every cell (section 2.1: the zeroth, first and second moments of
+ * the intensity, as radiation energy density, flux and pressure tensor).  With the
+ * intensities in energy-density units, E_r = 4 pi sum_k W_k I_k,
+ * F_r = 4 pi c sum_k W_k n_k I_k and P_r = 4 pi sum_k W_k n_k n_k I_k (c = c_light).
+ * I [N][K] (device, params->dtype); moments [N][10] (device, FP64, written):
+ * (E_r, F_x, F_y, F_z, P_xx, P_yy, P_zz, P_xy, P_xz, P_yz).  Only params->dtype and
+ * params->c_light are used (the other fields must still be valid).  Enqueues one
+ * kernel and never allocates.  RT_EINVAL if I and moments overlap.
+ */
+int rt_moments(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I, double *moments,
+               void *stream);
+
+/*
  * Conservation diagnostics into out[RT_NDIAG] (HOST): sum V E_g,
  * sum V (c/cbar) E_r, sum V rho v (3), sum V F_r/(c cbar) (3), min I, and the
  * number of non-finite entries of I, etot and mom.  Synchronises `stream`.

@@ -1,5 +1,6 @@
 // Grid reductions: conservation diagnostics (section 2.3.1) and the emergent-flux
-// loss with its seed.  Each cell group reduces over its angles, each workgroup
+// loss with its seed; and the per-cell angle moments (section 2.1), reduced over each
+// cell's lanes only.  Each cell group reduces over its angles, each workgroup
 // over its cells through LDS, then two folds over the per-workgroup partials in a
 // fixed order, so results are deterministic (no atomics).
 #include "rt_device.h"
@@ -165,6 +166,62 @@ __global__ __launch_bounds__(RT_BLOCK) void k_loss(int64_t N, int K, const int32
   block_reduce_store<1, LPC>(v, kind, partial + lb);
 }
 
+// Angle moments of every cell (section 2.1): with intensities in energy-density units,
+// E_r = 4 pi sum W I, F_r = 4 pi c sum W n I, P_r = 4 pi sum W n n I.  The LPC lanes of a
+// cell sum their angles; the group sums (DPP) leave the totals in every lane, and lane c
+// writes component c (two rounds when LPC = 8), so a cell's 80 bytes go out together.
+template <typename T, int LPC, int APL>
+__global__ __launch_bounds__(RT_BLOCK) void k_moments(int64_t N, int K, const double *dirs, const double *W,
+                                                      double c_light, const T *I, double *out, int64_t nblk) {
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  constexpr int CPB = RT_BLOCK / LPC;
+  const int64_t cell = lb * CPB + threadIdx.x / LPC;
+  if (cell >= N) return;  // whole lane groups
+  const int l = threadIdx.x % LPC;
+  rt_lane_angles<double, LPC, APL> ang;
+  ang.load(dirs, W, K, l);
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < APL; ++q) {
+    const double wI = ang.ok[q] ? ang.w[q] * (double)I[cell * (int64_t)K + ang.k[q]] : 0.0;
+    const double nx = ang.dx[q], ny = ang.dy[q], nz = ang.dz[q];
+    m[0] += wI;
+    m[1] += wI * nx;
+    m[2] += wI * ny;
+    m[3] += wI * nz;
+    m[4] += wI * nx * nx;
+    m[5] += wI * ny * ny;
+    m[6] += wI * nz * nz;
+    m[7] += wI * nx * ny;
+    m[8] += wI * nx * nz;
+    m[9] += wI * ny * nz;
+  }
+  const double fourpi = 4.0 * RT_PI;
+  double r[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) r[c] = rt_group_sum<LPC>(m[c]) * (c >= 1 && c <= 3 ? fourpi * c_light : fourpi);
+#pragma unroll
+  for (int c0 = 0; c0 < 10; c0 += LPC) {
+    // lane l writes component c0 + l
+    double v = r[c0];
+#pragma unroll
+    for (int c = c0 + 1; c < c0 + LPC && c < 10; ++c)
+      if (l == c - c0) v = r[c];
+    if (c0 + l < 10) out[10 * cell + c0 + l] = v;
+  }
+}
+
+template <typename T, int LPC, int APL>
+hipError_t launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
+                          double *out, hipStream_t s) {
+  const int64_t cpb = RT_BLOCK / LPC;
+  const int64_t nblk = (m->N + cpb - 1) / cpb;
+  hipLaunchKernelGGL((k_moments<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K,
+                     dirs, W, c_light, (const T *)I, out, nblk);
+  return hipGetLastError();
+}
+
 template <typename T, int LPC, int APL>
 hipError_t launch_diag(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red, double c_light,
                        const void *I, const double *vol, const double *etot, const double *mom, double *out,
@@ -229,6 +286,12 @@ hipError_t diag_t(const rt_mesh *m, int K, const double *dirs, const double *W, 
 }
 
 template <typename T>
+hipError_t moments_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
+                     double *out, hipStream_t s) {
+  RT_DISPATCH(launch_moments, T, m, K, dirs, W, c_light, I, out, s);
+}
+
+template <typename T>
 hipError_t loss_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
                   const double *fw, double *loss, void *seed, hipStream_t s) {
   RT_DISPATCH(launch_loss, T, m, K, dirs, W, c_light, I, fw, loss, seed, s);
@@ -248,4 +311,10 @@ hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, cons
                                hipStream_t s) {
   return dtype == RT_F32 ? loss_t<float>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s)
                          : loss_t<double>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s);
+}
+
+hipError_t rt_launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                             const void *I, double *out, int dtype, hipStream_t s) {
+  return dtype == RT_F32 ? moments_t<float>(m, K, dirs, W, c_light, I, out, s)
+                         : moments_t<double>(m, K, dirs, W, c_light, I, out, s);
 }

@@ -776,6 +776,21 @@ int rt_marked_apply(rt_mesh *m, const rt_params *p, const rt_angles *a, const rt
   return RT_OK;
 }
 
+int rt_moments(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, double *moments, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, moments}))) return rc;
+  {
+    const char *i0 = (const char *)I, *i1 = i0 + elem(p->dtype) * (size_t)m->N * (size_t)a->K;
+    const char *o0 = (const char *)moments, *o1 = o0 + sizeof(double) * 10 * (size_t)m->N;
+    if (i0 < o1 && o0 < i1) return fail(RT_EINVAL, "I and moments overlap");
+  }
+  hipError_t e = rt_launch_moments(m, a->K, a->dir, a->weight, p->c_light, I, moments, p->dtype,
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
+  return RT_OK;
+}
+
 int rt_diagnostics(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, const double *vol,
                    const double *etot, const double *mom, double *out, void *stream) {
   int rc = check_call(m, p, a);

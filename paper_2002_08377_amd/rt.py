@@ -64,6 +64,7 @@ _SIGS = {
     "rt_step_adjoint": [ctypes.c_void_p] * 17,
     "rt_flux_loss": [ctypes.c_void_p] * 8,
     "rt_diagnostics": [ctypes.c_void_p] * 9,
+    "rt_moments": [ctypes.c_void_p] * 6,
     "rt_angles_layout": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
     "rt_marked_upload": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 5
                         + [ctypes.c_double, ctypes.c_void_p],
@@ -397,6 +398,15 @@ def flux_loss(mesh, params, angles, I, face_weight, loss, seed=None, stream=None
                             _dev(loss, torch.float64, (1,), "loss"), _dev(seed, td, (N, K), "seed", True),
                             _stream(stream))
     _check("rt_flux_loss", rc)
+
+
+def moments(mesh, params, angles, I, out, stream=None):
+    """Per-cell angle moments into out [N, 10] (FP64): E_r, F_r (3), P_r (xx, yy, zz, xy, xz, yz)."""
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    rc = lib().rt_moments(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), _dev(I, td, (N, K), "I"),
+                          _dev(out, torch.float64, (N, 10), "moments"), _stream(stream))
+    _check("rt_moments", rc)
 
 
 def diagnostics(mesh, params, angles, I, vol, etot, mom, stream=None, allow_nonfinite=False):

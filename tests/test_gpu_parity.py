@@ -443,3 +443,31 @@ def test_largest_angle_sets_steps_match_oracle(dtype, K):
         assert rel_err(dp.T.cpu().numpy(), To) < 1e-12
         assert rel_err(dp.etot.cpu().numpy(), so.etot) < 1e-12
         assert rel_err(dp.mom.cpu().numpy(), so.mom) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("K", [8, 20, 24, 80, 120])
+def test_moments_match_oracle(dtype, K):
+    """Per-cell E_r, F_r, P_r (section 2.1) against the oracle on the stored intensities,
+    across the 8- and 16-lane layouts (K = 20: masked lanes); the sums are FP64 in both forms."""
+    p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
+    dp = DeviceProblem(p, dtype=dtype)
+    N = p.mesh.n_cells
+    out = torch.full((N, 10), float("nan"), dtype=torch.float64, device="cuda")
+    rt.moments(dp.mesh, dp.params, dp.angles, dp.I, out)
+    ref = orc.moments(p.dirs, p.weights, p.phys.c_light, dp.host(dp.I))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for cols in (slice(0, 1), slice(1, 4), slice(4, 10)):
+        assert rel_err(got[:, cols], ref[:, cols]) < 1e-13
+    # moments written over the intensities are refused
+    K_ = dp.I.shape[1]
+    if dtype == rt.F64:
+        buf = torch.zeros(N * K_ + 10 * N + 1, dtype=torch.float64, device="cuda")
+        I_a, m_a = buf[: N * K_].view(N, K_), buf[1: 1 + 10 * N].view(N, 10)
+    else:
+        buf = torch.zeros(N * K_ + 20 * N + 2, dtype=torch.float32, device="cuda")
+        I_a, m_a = buf[: N * K_].view(N, K_), buf[2: 2 + 20 * N].view(torch.float64).view(N, 10)
+    with pytest.raises(rt.RTError) as e:
+        rt.moments(dp.mesh, dp.params, dp.angles, I_a, m_a)
+    assert e.value.code == rt.RT_EINVAL
