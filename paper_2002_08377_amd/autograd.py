@@ -7,8 +7,10 @@ backward pass walks the segments in reverse: it restores the segment's
 checkpoint, re-runs its steps with the taped step call (the same fused kernel,
 so the same values bit for bit, which also stores the transported intensities
 I*), records the start-of-step volume and gas state, and then applies the
-per-step adjoint in reverse order.  Peak memory is therefore one checkpoint per segment plus
-`ckpt_every` recorded steps, instead of all S steps.
+per-step adjoint in reverse order.  The last segment is taped during the forward
+pass already (the backward starts there), so it is not run again.  Peak memory is
+therefore one checkpoint per segment plus `ckpt_every` recorded steps, instead of
+all S steps.
 
 The opacities are tied, kappa_P = kappa_J = kappa_a, so dL/dkappa_a is the sum
 of the two partial derivatives; the library increments both into one buffer.
@@ -63,16 +65,26 @@ class RTSteps(torch.autograd.Function):
         mom = mom0.detach().contiguous().clone()
         vol = system.vol0.detach().contiguous().clone()
         ckpts = []
+        last = ((n_steps - 1) // ckpt_every) * ckpt_every if n_steps else 0  # first step of the last segment
+        tape = []
         for n in range(n_steps):
             if n % ckpt_every == 0:
                 ckpts.append((I.clone(), etot.clone(), mom.clone(), vol.clone()))
-            rt.step(system.mesh, system.params, system.angles, I, I2, vol, system.rho, mom, etot, kap, kap,
-                    system.ks)
+            if n >= last:
+                # the last segment: tape it now (the taped step gives the fused step's values)
+                rec = (torch.empty_like(I), vol.clone(), mom.clone(), etot.clone())
+                rt.step_taped(system.mesh, system.params, system.angles, I, I2, rec[0], vol, system.rho, mom, etot,
+                              kap, kap, system.ks)
+                tape.append(rec)
+            else:
+                rt.step(system.mesh, system.params, system.angles, I, I2, vol, system.rho, mom, etot, kap, kap,
+                        system.ks)
             I, I2 = I2, I
         ctx.system = system
         ctx.n_steps = n_steps
         ctx.ckpt_every = ckpt_every
         ctx.ckpts = ckpts
+        ctx.last_tape = tape
         ctx.save_for_backward(kap)
         ctx.in_dtype = I0.dtype
         return I, etot, mom
@@ -92,22 +104,30 @@ class RTSteps(torch.autograd.Function):
                 else torch.zeros((N, 3), dtype=torch.float64, device=dev))
         dk = torch.zeros(N, dtype=torch.float64, device=dev)
         L = ctx.ckpt_every
-        tape_I = [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps))]
+        # the forward pass's I* buffers are reused for the recomputed segments once the last
+        # segment's adjoint steps (enqueued first, on the same stream) have read them
+        tape_I = [rec[0] for rec in ctx.last_tape]
+        tape_I += [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps) - len(tape_I))]
         I2 = torch.empty((N, K), dtype=td, device=dev)
         for seg in reversed(range(len(ctx.ckpts))):
-            I, etot, mom, vol = (t.clone() for t in ctx.ckpts[seg])
-            n0 = seg * L
-            nseg = min(L, ctx.n_steps - n0)
-            tape = []
-            for n in range(nseg):
-                vol_n, mom_n, etot_n = vol.clone(), mom.clone(), etot.clone()
-                rt.step_taped(s.mesh, s.params, s.angles, I, I2, tape_I[n], vol, s.rho, mom, etot, kap, kap, s.ks)
-                I, I2 = I2, I
-                tape.append((tape_I[n], vol_n, mom_n, etot_n))
+            if seg == len(ctx.ckpts) - 1:
+                tape = ctx.last_tape  # taped by the forward pass
+            else:
+                I, etot, mom, vol = (t.clone() for t in ctx.ckpts[seg])
+                n0 = seg * L
+                nseg = min(L, ctx.n_steps - n0)
+                tape = []
+                for n in range(nseg):
+                    vol_n, mom_n, etot_n = vol.clone(), mom.clone(), etot.clone()
+                    rt.step_taped(s.mesh, s.params, s.angles, I, I2, tape_I[n], vol, s.rho, mom, etot, kap, kap,
+                                  s.ks)
+                    I, I2 = I2, I
+                    tape.append((tape_I[n], vol_n, mom_n, etot_n))
             for I_star, vol_n, mom_n, etot_n in reversed(tape):
                 rt.step_adjoint(s.mesh, s.params, s.angles, I_star, vol_n, s.rho, mom_n, etot_n, kap, kap, s.ks,
                                 lamI, lamE, lamM, dk, dk)
         ctx.ckpts = None
+        ctx.last_tape = None
         return lamI.to(ctx.in_dtype), dk, lamE, lamM, None, None, None
 
 
