@@ -57,10 +57,26 @@ def test_upload_rejects_bad_meshes_on_the_host():
 
 
 def test_calls_reject_null_mesh():
+    """Every call that takes a mesh refuses a NULL one on the host, before any device work."""
     L = rt.lib()
     prm = rt.make_params(1.0, 1.0, 1.0, 1.5, 0.1)
     rc = L.rt_step(None, ctypes.byref(prm), None, *([None] * 11))
     assert rc == rt.RT_EINVAL
+    for name in ("rt_transport_step", "rt_source_implicit", "rt_step_taped", "rt_gradient", "rt_step_adjoint",
+                 "rt_flux_loss", "rt_moments", "rt_diagnostics", "rt_source_implicit_mg", "rt_step_mg",
+                 "rt_source_implicit_kT", "rt_step_kT", "rt_marked_apply"):
+        fn = getattr(L, name)
+        args = []
+        for i, t in enumerate(fn.argtypes):
+            if i == 1:
+                args.append(ctypes.byref(prm))
+            elif t is ctypes.c_double:
+                args.append(1.0)
+            elif t in (ctypes.c_int, ctypes.c_int32, ctypes.c_int64):
+                args.append(1)
+            else:
+                args.append(None)
+        assert fn(*args) == rt.RT_EINVAL, name
     assert L.rt_mesh_free(None) == rt.RT_OK
 
 
