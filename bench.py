@@ -471,10 +471,21 @@ def main():
         log(f"copy calibration: 3 negated copies of {N * K * 4} bytes")
         del x, y
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    # Angle order per form (the same directions; a storage choice of the caller): the FP32 form
+    # runs fastest with the antipode of angle k at k + K/2 (each lane's 4-byte accesses of a
+    # cell cover 32 contiguous bytes), the FP64 form with antipodes side by side (one 16-byte
+    # access per pair).  The FP64 result is put back in the first order for the comparison.
+    perm = inp.adjacent_pair_order(K)
+    setup = {"f32": (prob, angles, None),
+             "f64": (inp.with_angle_order(prob, perm), rt.AngleSet(prob.dirs[perm], prob.weights[perm]),
+                     np.argsort(perm))}
     res = {}
     for name, code in (("f32", rt.F32), ("f64", rt.F64)):
         if name in forms:
-            res[name] = run_form(prob, mesh, angles, code, args.steps, args.warmup, log)
+            p_form, a_form, inv = setup[name]
+            res[name] = run_form(p_form, mesh, a_form, code, args.steps, args.warmup, log)
+            if inv is not None:
+                res[name]["I"] = np.ascontiguousarray(res[name]["I"][:, inv])
     if not ("f32" in res and "f64" in res):
         mesh.free()
         print(json.dumps({name: {"ms_per_step": r["wall"] * 1e3 / args.steps, "kernel_ms": r["kernel_ms"]}
@@ -520,6 +531,8 @@ def main():
         "config": {"workload": f"throughput_{round(N ** (1 / 3))}c_{K}a", "cells": N, "faces": F, "angles": K,
                    "steps": args.steps, "scheme": "upwind1",
                    "precision": "FP32 intensities and transport, FP64 source solve and bookkeeping",
+                   "angle_order": "level-symmetric S8 set; antipode of angle k at k + K/2 (FP32 form), "
+                                  "at k + 1 for even k (FP64 form)",
                    "mesh": "periodic Voronoi of a +-0.2 jittered cubic lattice, Morton-ordered cells"},
         "roofline": roof("f32"),
         "fp64": {"value": ca / res["f64"]["wall"], "ms_per_step": res["f64"]["wall"] * 1e3 / args.steps,

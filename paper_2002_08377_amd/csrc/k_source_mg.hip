@@ -13,7 +13,7 @@
 
 namespace {
 
-template <typename T, int LPC, int APL, bool FULL, bool PAIRED>
+template <typename T, int LPC, int APL, bool FULL, int PAIRED>
 __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nblk) {
   using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED>;
   constexpr int P = Ang::P;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   }
 }
 
-template <typename T, int LPC, int APL, bool FULL, bool PAIRED>
+template <typename T, int LPC, int APL, bool FULL, int PAIRED>
 hipError_t launch(const rt_mg_args &a, hipStream_t s) {
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (a.N + cpb - 1) / cpb;
@@ -156,37 +156,43 @@ hipError_t launch(const rt_mg_args &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int PAIRED> hipError_t dispatch_paired(const rt_mg_args &a, hipStream_t s) {
+  switch (rt_paired_lanes(a.K)) {  // 0 (no paired layout for K) matches no case
+    case 0x0802: return launch<T, 8, 2, true, PAIRED>(a, s);
+    case 0x0804: return launch<T, 8, 4, true, PAIRED>(a, s);
+    case 0x0806: return launch<T, 8, 6, true, PAIRED>(a, s);
+    case 0x0808: return launch<T, 8, 8, true, PAIRED>(a, s);
+    case 0x080a: return launch<T, 8, 10, true, PAIRED>(a, s);
+    case 0x080c: return launch<T, 8, 12, true, PAIRED>(a, s);
+    case 0x0402: return launch<T, 4, 2, true, PAIRED>(a, s);
+    case 0x0406: return launch<T, 4, 6, true, PAIRED>(a, s);
+    case 0x040a: return launch<T, 4, 10, true, PAIRED>(a, s);
+  }
+  return hipErrorInvalidConfiguration;
+}
+
 template <typename T> hipError_t dispatch(const rt_mg_args &a, hipStream_t s) {
   if (a.paired) {
-    switch (rt_paired_lanes(a.K)) {  // 0 (no paired layout for K) matches no case
-      case 0x0802: return launch<T, 8, 2, true, true>(a, s);
-      case 0x0804: return launch<T, 8, 4, true, true>(a, s);
-      case 0x0806: return launch<T, 8, 6, true, true>(a, s);
-      case 0x0808: return launch<T, 8, 8, true, true>(a, s);
-      case 0x080a: return launch<T, 8, 10, true, true>(a, s);
-      case 0x080c: return launch<T, 8, 12, true, true>(a, s);
-      case 0x0402: return launch<T, 4, 2, true, true>(a, s);
-      case 0x0406: return launch<T, 4, 6, true, true>(a, s);
-      case 0x040a: return launch<T, 4, 10, true, true>(a, s);
-    }
+    const hipError_t e = a.paired == 2 ? dispatch_paired<T, 2>(a, s) : dispatch_paired<T, 1>(a, s);
+    if (e != hipErrorInvalidConfiguration) return e;
   }
   switch (rt_step_lanes(a.K, 0)) {
-    case 0x1001: return launch<T, 16, 1, false, false>(a, s);
-    case 0x1002: return launch<T, 16, 2, false, false>(a, s);
-    case 0x1003: return launch<T, 16, 3, false, false>(a, s);
-    case 0x1004: return launch<T, 16, 4, false, false>(a, s);
-    case 0x1005: return launch<T, 16, 5, false, false>(a, s);
-    case 0x1006: return launch<T, 16, 6, false, false>(a, s);
-    case 0x1007: return launch<T, 16, 7, false, false>(a, s);
-    case 0x1008: return launch<T, 16, 8, false, false>(a, s);
-    case 0x0801: return launch<T, 8, 1, false, false>(a, s);
-    case 0x0802: return launch<T, 8, 2, false, false>(a, s);
-    case 0x0803: return launch<T, 8, 3, false, false>(a, s);
-    case 0x0804: return launch<T, 8, 4, false, false>(a, s);
-    case 0x0805: return launch<T, 8, 5, false, false>(a, s);
-    case 0x0806: return launch<T, 8, 6, false, false>(a, s);
-    case 0x0807: return launch<T, 8, 7, false, false>(a, s);
-    case 0x0808: return launch<T, 8, 8, false, false>(a, s);
+    case 0x1001: return launch<T, 16, 1, false, 0>(a, s);
+    case 0x1002: return launch<T, 16, 2, false, 0>(a, s);
+    case 0x1003: return launch<T, 16, 3, false, 0>(a, s);
+    case 0x1004: return launch<T, 16, 4, false, 0>(a, s);
+    case 0x1005: return launch<T, 16, 5, false, 0>(a, s);
+    case 0x1006: return launch<T, 16, 6, false, 0>(a, s);
+    case 0x1007: return launch<T, 16, 7, false, 0>(a, s);
+    case 0x1008: return launch<T, 16, 8, false, 0>(a, s);
+    case 0x0801: return launch<T, 8, 1, false, 0>(a, s);
+    case 0x0802: return launch<T, 8, 2, false, 0>(a, s);
+    case 0x0803: return launch<T, 8, 3, false, 0>(a, s);
+    case 0x0804: return launch<T, 8, 4, false, 0>(a, s);
+    case 0x0805: return launch<T, 8, 5, false, 0>(a, s);
+    case 0x0806: return launch<T, 8, 6, false, 0>(a, s);
+    case 0x0807: return launch<T, 8, 7, false, 0>(a, s);
+    case 0x0808: return launch<T, 8, 8, false, 0>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -21,7 +21,7 @@ template <typename T> struct rt_batch { static constexpr int U = 2; };
 // The cells of a workgroup are consecutive, so their half-faces form one contiguous
 // range; it is staged in LDS (dynamic size: the largest range of any workgroup,
 // found at upload) and the face loops read their records from there.
-template <typename T, int LPC, int APL, int MODE, bool FULL, bool PAIRED>
+template <typename T, int LPC, int APL, int MODE, bool FULL, int PAIRED>
 __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
   using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED>;
@@ -64,8 +64,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   const T *Iin = (const T *)a.I_in;
   const int64_t row = cell * (int64_t)K;
   T Ic[APL];
-#pragma unroll
-  for (int q = 0; q < APL; ++q) Ic[q] = Iin[row + ang.k[q]];
+  ang.read_row(Iin + row, Ic);
 
   double Vnew = 0.0;
   if (MODE != 0) {
@@ -94,9 +93,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
         }
         T xn[U][APL];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int q = 0; q < APL; ++q) xn[u][q] = Iin[j[u] * K + ang.k[q]];
+        for (int u = 0; u < U; ++u) ang.read_row(Iin + j[u] * K, xn[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           // g = dt (cbar (A n_out).n_k - A (w~.n)_out): charge leaving per unit upwind intensity
@@ -188,12 +185,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
       for (int q = 0; q < APL; ++q) Ic[q] = Ic[q] * cr + acc[q] * ci;
     }
     if constexpr (MODE == 1) {
-      if (a.I_star_out) {
-        T *Ist = (T *)a.I_star_out;
-#pragma unroll
-        for (int q = 0; q < APL; ++q)
-          if (ang.ok[q]) Ist[row + ang.k[q]] = Ic[q];
-      }
+      if (a.I_star_out) ang.write_row((T *)a.I_star_out + row, Ic);
     }
   }
 
@@ -201,17 +193,14 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
     if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
   }
 
-  T *Iout = (T *)a.I_out;
-#pragma unroll
-  for (int q = 0; q < APL; ++q)
-    if (ang.ok[q]) Iout[row + ang.k[q]] = Ic[q];
+  ang.write_row((T *)a.I_out + row, Ic);
   if ((MODE == 1 || MODE == 2) && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
 }
 
 // Staging needs (records per half-face) x (half-faces of the largest range of the
 // workgroup's cells) bytes of LDS; a layout that would need more than 64 KiB is
 // refused with hipErrorInvalidConfiguration (the dispatch then tries another).
-template <typename T, int LPC, int APL, bool FULL, bool PAIRED>
+template <typename T, int LPC, int APL, bool FULL, int PAIRED>
 hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
   using V4 = typename rt_vec4<T>::type;
   rt_step_args a = args;
@@ -234,21 +223,21 @@ hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
 }
 
 template <typename T, int LPC, int APL> hipError_t launch(const rt_step_args &a, hipStream_t s) {
-  return a.K == LPC * APL ? launch_mode<T, LPC, APL, true, false>(a, s)
-                          : launch_mode<T, LPC, APL, false, false>(a, s);
+  return a.K == LPC * APL ? launch_mode<T, LPC, APL, true, 0>(a, s)
+                          : launch_mode<T, LPC, APL, false, 0>(a, s);
 }
 
-template <typename T> hipError_t dispatch_paired(const rt_step_args &a, hipStream_t s) {
+template <typename T, int PAIRED> hipError_t dispatch_paired(const rt_step_args &a, hipStream_t s) {
   switch (rt_paired_lanes(a.K)) {  // 0 (no paired layout for K) matches no case
-    case 0x0802: return launch_mode<T, 8, 2, true, true>(a, s);
-    case 0x0804: return launch_mode<T, 8, 4, true, true>(a, s);
-    case 0x0806: return launch_mode<T, 8, 6, true, true>(a, s);
-    case 0x0808: return launch_mode<T, 8, 8, true, true>(a, s);
-    case 0x080a: return launch_mode<T, 8, 10, true, true>(a, s);
-    case 0x080c: return launch_mode<T, 8, 12, true, true>(a, s);
-    case 0x0402: return launch_mode<T, 4, 2, true, true>(a, s);
-    case 0x0406: return launch_mode<T, 4, 6, true, true>(a, s);
-    case 0x040a: return launch_mode<T, 4, 10, true, true>(a, s);
+    case 0x0802: return launch_mode<T, 8, 2, true, PAIRED>(a, s);
+    case 0x0804: return launch_mode<T, 8, 4, true, PAIRED>(a, s);
+    case 0x0806: return launch_mode<T, 8, 6, true, PAIRED>(a, s);
+    case 0x0808: return launch_mode<T, 8, 8, true, PAIRED>(a, s);
+    case 0x080a: return launch_mode<T, 8, 10, true, PAIRED>(a, s);
+    case 0x080c: return launch_mode<T, 8, 12, true, PAIRED>(a, s);
+    case 0x0402: return launch_mode<T, 4, 2, true, PAIRED>(a, s);
+    case 0x0406: return launch_mode<T, 4, 6, true, PAIRED>(a, s);
+    case 0x040a: return launch_mode<T, 4, 10, true, PAIRED>(a, s);
   }
   return hipErrorInvalidConfiguration;
 }
@@ -279,7 +268,7 @@ template <typename T> hipError_t dispatch_general(const rt_step_args &a, hipStre
 // fits in LDS; everything else (and that fallback) the general kernel.
 template <typename T> hipError_t dispatch(const rt_step_args &a, hipStream_t s) {
   if (a.paired) {
-    const hipError_t e = dispatch_paired<T>(a, s);
+    const hipError_t e = a.paired == 2 ? dispatch_paired<T, 2>(a, s) : dispatch_paired<T, 1>(a, s);
     if (e != hipErrorInvalidConfiguration) return e;
   }
   return dispatch_general<T>(a, s);

@@ -61,7 +61,8 @@ int check_call(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
   if (a->K < 1 || a->K > m->k_max || a->K > RT_K_MAX)
     return fail(RT_EINVAL, "K=%d outside [1, k_max=%d]", a->K, m->k_max);
   if (!a->dir || !a->weight) return fail(RT_EINVAL, "angle arrays are NULL");
-  if (a->layout != RT_ANGLES_GENERAL && !(a->layout == RT_ANGLES_ANTIPODAL && a->K % 2 == 0))
+  if (a->layout != RT_ANGLES_GENERAL &&
+      !((a->layout == RT_ANGLES_ANTIPODAL || a->layout == RT_ANGLES_ANTIPODAL_ADJACENT) && a->K % 2 == 0))
     return fail(RT_EINVAL, "invalid angle layout %d for K=%d", a->layout, a->K);
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(RT_EINVAL, "dt must be positive and finite");
   if (!(p->c_red > 0.0) || !isfinite(p->c_red)) return fail(RT_EINVAL, "c_red must be positive");
@@ -109,7 +110,7 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
   s.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
   s.m_gain = 4.0 * M_PI / p->c_red;
   s.a_4pi = p->a_rad / (4.0 * M_PI);
-  s.paired = a->layout == RT_ANGLES_ANTIPODAL;
+  s.paired = rt_pair_kind(a->layout);
   s.hf_cap16 = m->hf_cap16;
   s.hf_cap32 = m->hf_cap32;
   s.hf_cap64 = m->hf_cap64;
@@ -201,13 +202,19 @@ int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t
   if (K < 1 || K > RT_K_MAX) return fail(RT_EINVAL, "K=%d outside [1, %d]", K, RT_K_MAX);
   *layout = RT_ANGLES_GENERAL;
   if (K % 2) return RT_OK;
-  const int h = K / 2;
-  for (int k = 0; k < h; ++k) {
-    if (weight[k + h] != weight[k]) return RT_OK;
-    for (int c = 0; c < 3; ++c)
-      if (dir[3 * (k + h) + c] != -dir[3 * k + c]) return RT_OK;
-  }
-  *layout = RT_ANGLES_ANTIPODAL;
+  // is angle b(k) the exact antipode of angle a(k), with its weight, for every k < K/2?
+  auto pairs = [&](auto a, auto b) {
+    for (int k = 0; k < K / 2; ++k) {
+      if (weight[b(k)] != weight[a(k)]) return false;
+      for (int c = 0; c < 3; ++c)
+        if (dir[3 * b(k) + c] != -dir[3 * a(k) + c]) return false;
+    }
+    return true;
+  };
+  if (pairs([](int k) { return k; }, [K](int k) { return k + K / 2; }))
+    *layout = RT_ANGLES_ANTIPODAL;
+  else if (pairs([](int k) { return 2 * k; }, [](int k) { return 2 * k + 1; }))
+    *layout = RT_ANGLES_ANTIPODAL_ADJACENT;
   return RT_OK;
 }
 
@@ -567,7 +574,7 @@ int rt_source_implicit_mg(rt_mesh *m, const rt_params *p, const rt_angles *a, in
   g.N = m->N;
   g.K = a->K;
   g.G = G;
-  g.paired = a->layout == RT_ANGLES_ANTIPODAL;
+  g.paired = rt_pair_kind(a->layout);
   g.dirs = a->dir;
   g.W = a->weight;
   g.Wg = group_weight;
@@ -653,7 +660,7 @@ int rt_source_implicit_kT(rt_mesh *m, const rt_params *p, const rt_angles *a, vo
   g.dt = p->dt;
   g.e_gain = 4.0 * M_PI * p->c_light / p->c_red;
   g.m_gain = 4.0 * M_PI / p->c_red;
-  g.paired = a->layout == RT_ANGLES_ANTIPODAL;
+  g.paired = rt_pair_kind(a->layout);
   hipError_t e = rt_launch_source_kT(g, p->dtype, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "temperature-dependent-opacity source kernel launch");
   return RT_OK;

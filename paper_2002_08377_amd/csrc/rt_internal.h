@@ -78,7 +78,7 @@ struct rt_step_args {
   double e_gain;      // 4 pi c / cbar: gas energy per unit of sum W (I - I')
   double m_gain;      // 4 pi / cbar: gas momentum per unit of sum W n (I - I')
   double a_4pi;       // a / 4 pi
-  int paired;        // angles in the RT_ANGLES_ANTIPODAL layout
+  int paired;        // rt_pair_kind of the angle layout
   int hf_cap;        // LDS staging slots of the launched kernel (set at dispatch)
   int hf_cap16, hf_cap32, hf_cap64;  // half-faces of the largest range of 16 / 32 / 64 cells
   const uint8_t *wg_order16, *wg_order32, *wg_order64;  // cell order within workgroups
@@ -109,6 +109,11 @@ static inline int rt_paired_lanes(int K) {
     if (half % 4 == 0 && (K / 4 == 2 || K / 4 == 6 || K / 4 == 10)) return (4 << 8) | (K / 4);
   }
   return 0;
+}
+// The paired lane layout of the kernels for an angle layout: 1 (antipode at k + K/2),
+// 2 (antipode at k + 1, pairs adjacent), 0 (none).
+static inline int rt_pair_kind(int layout) {
+  return layout == RT_ANGLES_ANTIPODAL ? 1 : layout == RT_ANGLES_ANTIPODAL_ADJACENT ? 2 : 0;
 }
 static inline int rt_step_lanes(int K, int paired) {
   if (paired && rt_paired_lanes(K)) return rt_paired_lanes(K);
@@ -181,7 +186,7 @@ struct rt_kT_args {
   double T_ref, bP, bJ;
   double c_red, c_light, a_rad, cv, dt;
   double e_gain, m_gain;
-  int paired;  // angles in the RT_ANGLES_ANTIPODAL layout
+  int paired;  // rt_pair_kind of the angle layout
 };
 hipError_t rt_launch_source_kT(const rt_kT_args &a, int dtype, hipStream_t s);
 

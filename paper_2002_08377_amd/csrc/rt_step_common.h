@@ -7,13 +7,17 @@
 // Angles held by one lane.
 //  General layout: k_q = l + LPC q for q < APL; past K (only when !FULL) the slot
 //    aliases angle 0 with weight 0 and is never stored.
-//  Paired layout (angle k + K/2 is the antipode of angle k and has its weight; needs
-//    K = LPC APL): the lane holds P = APL/2 angles k_q = l + LPC q and their
-//    antipodes k_q + K/2 in slots q + P, so one stored direction serves both and
+//  Paired layouts (needs K = LPC APL): the lane holds P = APL/2 angles and their
+//    antipodes (same weight) in slots q + P, so one stored direction serves both and
 //    one dot product per face serves both fluxes.
-template <typename T, int LPC, int APL, bool FULL, bool PAIRED> struct rt_step_angles {
+//    PAIRED 1, antipode of angle k at k + K/2: angles k_q = l + LPC q and k_q + K/2.
+//    PAIRED 2, antipode of angle 2p at 2p + 1: pairs p_q = l + LPC q, angles 2 p_q and
+//      2 p_q + 1, adjacent in a row, so one 2-element load or store moves both and the
+//      LPC lanes of a cell cover 2 LPC consecutive elements per access.
+template <typename T, int LPC, int APL, bool FULL, int PAIRED> struct rt_step_angles {
   static constexpr int P = PAIRED ? APL / 2 : APL;
-  static constexpr bool PAIRED_LAYOUT = PAIRED;
+  static constexpr bool PAIRED_LAYOUT = PAIRED != 0;
+  static constexpr bool ADJACENT = PAIRED == 2;
   T x[P], y[P], z[P];
   double w[P];
   int k[APL];
@@ -21,7 +25,7 @@ template <typename T, int LPC, int APL, bool FULL, bool PAIRED> struct rt_step_a
   __device__ __forceinline__ void load(const double *dirs, const double *W, int K, int l) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const int kk = l + LPC * q;
+      const int kk = PAIRED == 2 ? 2 * (l + LPC * q) : l + LPC * q;
       ok[q] = FULL || PAIRED || kk < K;
       k[q] = ok[q] ? kk : 0;
       x[q] = (T)dirs[3 * k[q]];
@@ -29,7 +33,7 @@ template <typename T, int LPC, int APL, bool FULL, bool PAIRED> struct rt_step_a
       z[q] = (T)dirs[3 * k[q] + 2];
       w[q] = ok[q] ? W[k[q]] : 0.0;
       if (PAIRED) {
-        k[q + P] = k[q] + K / 2;
+        k[q + P] = k[q] + (PAIRED == 2 ? 1 : K / 2);
         ok[q + P] = true;
       }
     }
@@ -39,6 +43,18 @@ template <typename T, int LPC, int APL, bool FULL, bool PAIRED> struct rt_step_a
   __device__ __forceinline__ T dy(int q) const { return PAIRED && q >= P ? -y[q - P] : y[q]; }
   __device__ __forceinline__ T dz(int q) const { return PAIRED && q >= P ? -z[q - P] : z[q]; }
   __device__ __forceinline__ double wt(int q) const { return PAIRED && q >= P ? w[q - P] : w[q]; }
+  // the lane's elements of the row starting at p (in the adjacent layout the two elements
+  // of a pair are consecutive, and the compiler moves them with one wider access: the
+  // arrays are only element-aligned, which the target's unaligned access mode allows)
+  __device__ __forceinline__ void read_row(const T *p, T (&v)[APL]) const {
+#pragma unroll
+    for (int q = 0; q < APL; ++q) v[q] = p[k[q]];
+  }
+  __device__ __forceinline__ void write_row(T *p, const T (&v)[APL]) const {
+#pragma unroll
+    for (int q = 0; q < APL; ++q)
+      if (ok[q]) p[k[q]] = v[q];
+  }
 };
 
 // Implicit source update (section 2.3, the four-step algorithm) of the cell `cell`,

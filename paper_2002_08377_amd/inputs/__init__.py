@@ -18,6 +18,7 @@ same arrays from here; neither imports the other.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -208,6 +209,19 @@ def angle_set(K: int) -> tuple[np.ndarray, np.ndarray]:
     return np.ascontiguousarray(d), w
 
 
+def adjacent_pair_order(K: int) -> np.ndarray:
+    """Permutation taking an angle set whose direction k + K/2 is the antipode of direction k
+    (the order of ``angle_set``) to the order in which direction 2p + 1 is the antipode of
+    direction 2p: new position 2p holds old angle p, new position 2p + 1 old angle p + K/2.
+    Index any per-angle array with it (``dirs[perm]``, ``I[:, perm]``)."""
+    if K % 2:
+        raise ValueError("an antipodal set has an even number of angles")
+    perm = np.empty(K, dtype=np.int64)
+    perm[0::2] = np.arange(K // 2)
+    perm[1::2] = np.arange(K // 2) + K // 2
+    return perm
+
+
 # ----------------------------------------------------------------------------------------------
 # workloads
 # ----------------------------------------------------------------------------------------------
@@ -272,6 +286,13 @@ class Problem:
     scheme: str
     config: Config | None = None
     seeds: dict = field(default_factory=dict)
+
+
+def with_angle_order(prob: Problem, perm: np.ndarray) -> Problem:
+    """The same problem with its angles (directions, weights, intensity columns) permuted."""
+    st = dataclasses.replace(prob.state, I=np.ascontiguousarray(prob.state.I[:, perm]))
+    return dataclasses.replace(prob, dirs=np.ascontiguousarray(prob.dirs[perm]),
+                               weights=np.ascontiguousarray(prob.weights[perm]), state=st)
 
 
 SEED_STREAMS = ("jitter", "rho", "T", "v", "kappa", "I_noise", "omega", "fd_cells")

@@ -45,7 +45,7 @@ class _Angles(ctypes.Structure):
 
 
 CELL_BOUNDARY, CELL_EMITTER = 1, 2
-ANGLES_GENERAL, ANGLES_ANTIPODAL = 0, 1
+ANGLES_GENERAL, ANGLES_ANTIPODAL, ANGLES_ANTIPODAL_ADJACENT = 0, 1, 2
 
 
 _lib = None
@@ -136,7 +136,7 @@ def torch_dtype(dtype: int):
 
 
 def angles_layout(dirs, weights) -> int:
-    """The library's classification of a host angle set (ANGLES_ANTIPODAL or ANGLES_GENERAL)."""
+    """The library's classification of a host angle set (one of the ANGLES_* values)."""
     d = np.ascontiguousarray(dirs, dtype=np.float64)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     out = ctypes.c_int32(-1)

@@ -98,6 +98,20 @@ def test_angle_layout_detection():
         w2 = w.copy(); w2[0] *= 1.0 + 1e-15
         assert rt.angles_layout(d, w2) == rt.ANGLES_GENERAL
         assert rt.angles_layout(d[:-1], w[:-1]) == rt.ANGLES_GENERAL
+        # antipodes side by side
+        perm = inp.adjacent_pair_order(K)
+        da, wa = d[perm], w[perm]
+        assert rt.angles_layout(da, wa) == rt.ANGLES_ANTIPODAL_ADJACENT
+        da2 = da.copy(); da2[3] = da2[2]
+        assert rt.angles_layout(da2, wa) == rt.ANGLES_GENERAL
+        wa2 = wa.copy(); wa2[K - 1] *= 1.0 + 1e-15
+        assert rt.angles_layout(da, wa2) == rt.ANGLES_GENERAL
+        # swapping two pairs keeps every pair adjacent
+        sw = np.arange(K); sw[[0, 1, 2, 3]] = [2, 3, 0, 1]
+        assert rt.angles_layout(da[sw], wa[sw]) == rt.ANGLES_ANTIPODAL_ADJACENT
+    # a two-angle set satisfies both definitions: the K/2 one is reported
+    d2 = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    assert rt.angles_layout(d2, np.array([0.5, 0.5])) == rt.ANGLES_ANTIPODAL
     L = rt.lib()
     out = ctypes.c_int32()
     assert L.rt_angles_layout(0, None, None, ctypes.byref(out)) == rt.RT_EINVAL

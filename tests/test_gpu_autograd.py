@@ -69,9 +69,11 @@ def _loss_fwd(system, x, fw, steps, gas_w=None):
 
 @pytest.mark.parametrize("K", [24, 80])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL, "adjacent"])
 def test_fused_step_equals_split_calls_bitwise(dtype, K, layout):
     p = inp.make_problem(0, n=7, K=K, steps=1)
+    if layout == "adjacent":  # antipodes side by side
+        p, layout = inp.with_angle_order(p, inp.adjacent_pair_order(K)), None
     st = p.state
     system, x = _system(p, dtype, layout)
     td = rt.torch_dtype(dtype)

@@ -33,10 +33,16 @@ def _mg_problem(K, G=3, n=7, seed=5):
     return p, np.ascontiguousarray(I), kP, kJ, ks, Wg
 
 
+@pytest.mark.parametrize("adjacent", [False, True])
 @pytest.mark.parametrize("K", [24, 80])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_source_mg_matches_oracle(dtype, K):
+def test_source_mg_matches_oracle(dtype, K, adjacent):
+    """adjacent: the angles reordered so that each antipodal pair sits side by side."""
     p, I, kP, kJ, ks, Wg = _mg_problem(K)
+    if adjacent:
+        perm = inp.adjacent_pair_order(K)
+        p, I = inp.with_angle_order(p, perm), np.ascontiguousarray(I[:, :, perm])
+        assert rt.angles_layout(p.dirs, p.weights) == rt.ANGLES_ANTIPODAL_ADJACENT
     st, ph = p.state, p.phys
     mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
     ang = rt.AngleSet(p.dirs, p.weights)

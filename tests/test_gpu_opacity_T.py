@@ -23,14 +23,17 @@ def _d(a):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
 
 
-@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
+@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL, "adjacent"])
 @pytest.mark.parametrize("bP,bJ", LAWS)
 @pytest.mark.parametrize("K", [24, 80])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 def test_source_kT_matches_oracle(dtype, K, bP, bJ, layout):
     """layout None: detected (antipodal sets take the paired 4/8-lane kernels); GENERAL: the
-    16/8-lane general kernel."""
+    16/8-lane general kernel; adjacent: the angles reordered so that each antipodal pair sits
+    side by side (the paired kernels in that layout)."""
     p = inp.make_problem(0, n=7, K=K, steps=1)
+    if layout == "adjacent":
+        p, layout = inp.with_angle_order(p, inp.adjacent_pair_order(K)), None
     st, ph = p.state, p.phys
     mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
     ang = rt.AngleSet(p.dirs, p.weights, layout=layout)

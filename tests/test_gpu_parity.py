@@ -21,6 +21,24 @@ pytestmark = pytest.mark.gpu
 
 TOL = {rt.F64: 1e-12, rt.F32: 1e-5}
 
+# layout case "adjacent": the same problem with its angles reordered so that each antipodal
+# pair sits side by side (RT_ANGLES_ANTIPODAL_ADJACENT, detected by the library)
+ADJ = "adjacent"
+LAYOUTS = [None, rt.ANGLES_GENERAL, ADJ]
+
+
+def _with_layout(p, layout):
+    if layout != ADJ:
+        return p, layout
+    q = inp.with_angle_order(p, inp.adjacent_pair_order(p.dirs.shape[0]))
+    assert rt.angles_layout(q.dirs, q.weights) == rt.ANGLES_ANTIPODAL_ADJACENT
+    return q, None
+
+
+def _cases(Ks):
+    """(K, layout) pairs; the K = 20 set (not antipodal) has no adjacent case."""
+    return [(K, l) for K in Ks for l in LAYOUTS if not (K == 20 and l == ADJ)]
+
 
 def _prob(index=0, n=7, K=24, steps=3):
     p = inp.make_problem(index, n=n, K=K, steps=steps)
@@ -46,12 +64,12 @@ def test_mesh_geometry_matches_oracle():
     assert info["n_half_faces"] == 2 * p.mesh.n_faces
 
 
-@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-@pytest.mark.parametrize("K", [8, 20, 24, 48, 80])
+@pytest.mark.parametrize("K,layout", _cases([8, 20, 24, 48, 80]))
 def test_transport_matches_oracle(dtype, K, layout):
-    """layout None: detected (antipodal sets take the paired kernel); GENERAL: forced general kernel."""
-    p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
+    """layout None: detected (antipodal sets take the paired kernel); GENERAL: forced general
+    kernel; adjacent: antipodes side by side (the paired kernel's 2-element accesses)."""
+    p, layout = _with_layout(_masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K), layout)
     dp = DeviceProblem(p, dtype=dtype, layout=layout)
     st = p.state
     rt.transport_step(dp.mesh, dp.params, dp.angles, dp.I, dp.I2, dp.vol)
@@ -61,11 +79,10 @@ def test_transport_matches_oracle(dtype, K, layout):
     assert rel_err(dp.vol.cpu().numpy(), vo) < 1e-15
 
 
-@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-@pytest.mark.parametrize("K", [8, 20, 24, 48, 80])
+@pytest.mark.parametrize("K,layout", _cases([8, 20, 24, 48, 80]))
 def test_source_matches_oracle(dtype, K, layout):
-    p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
+    p, layout = _with_layout(_masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K), layout)
     dp = DeviceProblem(p, dtype=dtype, layout=layout)
     st = p.state
     # stiffen half the cells
@@ -83,11 +100,11 @@ def test_source_matches_oracle(dtype, K, layout):
     assert rel_err(dp.mom.cpu().numpy(), mo) < max(tol_gas, 1e-12)
 
 
-@pytest.mark.parametrize("layout", [None, rt.ANGLES_GENERAL])
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 def test_forward_12c_24a_10steps(dtype, layout):
     """The plain forward workload at its full size: 12^3 cells, 24 angles, 10 steps."""
-    p = inp.make_problem(0)
+    p, layout = _with_layout(inp.make_problem(0), layout)
     dp = DeviceProblem(p, dtype=dtype, layout=layout)
     dp.run_gpu(p.steps)
     so, To = dp.run_oracle(p.steps)
@@ -131,10 +148,11 @@ def test_gradient_matches_oracle(dtype):
     assert rel_err(dp.host(g), go) < (1e-11 if dtype == rt.F64 else 1e-4)
 
 
+@pytest.mark.parametrize("layout", [None, ADJ])
 @pytest.mark.parametrize("K", [24, 48])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_plm_steps_match_oracle(dtype, K):
-    p = _prob(1, n=9, K=K, steps=4)
+def test_plm_steps_match_oracle(dtype, K, layout):
+    p, _ = _with_layout(_prob(1, n=9, K=K, steps=4), layout)
     dp = DeviceProblem(p, dtype=dtype, scheme=rt.PLM_VL2)
     dp.run_gpu(4)
     so, To = dp.run_oracle(4, "plm_vl2")
@@ -179,14 +197,20 @@ def throughput_problem():
     return p, so, To
 
 
-@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_throughput_128c_80a_one_step(dtype, throughput_problem):
-    """The throughput workload at full size in the launch the bench times (fused step, paired
-    lane layout, 2,097,152 cells x 80 angles): every cell and angle against the oracle."""
+@pytest.mark.parametrize("dtype,order", [(rt.F64, "half"), (rt.F32, "half"), (rt.F64, ADJ)])
+def test_throughput_128c_80a_one_step(dtype, order, throughput_problem):
+    """The throughput workload at full size in the launches the bench times (fused step, paired
+    lane layouts, 2,097,152 cells x 80 angles; the FP64 form is timed with antipodes side by
+    side): every cell and angle against the oracle."""
     p, so, To = throughput_problem
+    if order == ADJ:
+        perm = inp.adjacent_pair_order(80)
+        p = inp.with_angle_order(p, perm)
+        so = orc.OState(np.ascontiguousarray(so.I[:, perm]), so.vol, so.mom, so.etot)
     st = p.state
     mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=80)
     ang = rt.AngleSet(p.dirs, p.weights)
+    assert ang.layout == (rt.ANGLES_ANTIPODAL_ADJACENT if order == ADJ else rt.ANGLES_ANTIPODAL)
     prm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, p.dt, dtype)
     td = rt.torch_dtype(dtype)
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
@@ -221,11 +245,14 @@ def test_flux_loss_and_seed_match_oracle():
     assert rel_err(seed.cpu().numpy() - 0.5, so) < 1e-13
 
 
+@pytest.mark.parametrize("layout", [None, ADJ])
 @pytest.mark.parametrize("K", [24, 80, 120])
-def test_adjoint_matches_oracle(K):
+def test_adjoint_matches_oracle(K, layout):
     """Reverse of 4 steps against the oracle's reverse mode: K = 24 (16 lanes x 2 angles), 80
-    (16 x 5) and 120, the largest level-symmetric set (16 x 8, every lane slot used)."""
-    p = _prob(2, n=8, K=K, steps=4)
+    (16 x 5) and 120, the largest level-symmetric set (16 x 8, every lane slot used); the
+    transpose transport in the paired layouts of K = 24 and 80, antipodes K/2 apart or side by
+    side (K = 120 has no paired layout: the general kernel serves both orders)."""
+    p, _ = _with_layout(_prob(2, n=8, K=K, steps=4), layout)
     st = p.state
     dp = DeviceProblem(p, flags=rt.MESH_ADJOINT)
     # forward on the GPU, recording the source inputs of every step
