@@ -175,17 +175,20 @@ def run_plm(log):
     import torch
     from paper_2002_08377_amd import inputs as inp
     from paper_2002_08377_amd import rt
-    p = inp.make_problem(1)
-    st, ph = p.state, p.phys
-    N, K = st.I.shape
+    p0 = inp.make_problem(1)
+    N, K = p0.state.I.shape
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
-    angles = rt.AngleSet(p.dirs, p.weights)
-    out = {"workload": f"plm_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p.steps,
-           "scheme": "plm_vl2"}
+    # each form in its faster angle order, as in the step measurement
+    orders = {"f64": inp.with_angle_order(p0, inp.adjacent_pair_order(K)), "f32": p0}
+    out = {"workload": f"plm_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p0.steps,
+           "scheme": "plm_vl2", "angle_order": {"f64": "antipodes adjacent", "f32": "antipode at k + K/2"}}
     for still in (False, True):
-        w = np.zeros_like(st.mesh_vel) if still else st.mesh_vel
-        mesh = rt.Mesh.from_inputs(p.mesh, w, k_max=K, flags=rt.MESH_PLM)
+        w = np.zeros_like(p0.state.mesh_vel) if still else p0.state.mesh_vel
+        mesh = rt.Mesh.from_inputs(p0.mesh, w, k_max=K, flags=rt.MESH_PLM)
         for name, code in (("f64", rt.F64), ("f32", rt.F32)):
+            p = orders[name]
+            st, ph = p.state, p.phys
+            angles = rt.AngleSet(p.dirs, p.weights)
             prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, code, rt.PLM_VL2)
             td = rt.torch_dtype(code)
             I = d(st.I).to(td)

@@ -239,8 +239,10 @@ int rt_gradient(rt_mesh *mesh, const rt_params *params, const rt_angles *angles,
  * dL/d(etot, mom)^n on return; dL_dkP, dL_dkJ [N] are incremented (nullable;
  * they may be the same array, which then receives both partials: the gradient
  * with respect to a tied opacity kP = kJ).
- * The temperature root enters through the implicit function theorem.  Needs a
- * mesh uploaded with RT_MESH_ADJOINT (RT_ESTATE otherwise).
+ * The temperature root enters through the implicit function theorem.  As in the
+ * forward source, the per-angle arithmetic is done in the intensities' type (FP32
+ * with RT_F32) and every sum over angles and every per-cell value in FP64.  Needs
+ * a mesh uploaded with RT_MESH_ADJOINT (RT_ESTATE otherwise).
  */
 int rt_step_adjoint(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_star,
                     const double *vol_n, const double *rho, const double *mom_n, const double *etot_n,

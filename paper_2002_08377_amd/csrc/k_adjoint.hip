@@ -22,7 +22,10 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   if (cell >= a.N) return;
   const int l = threadIdx.x % LPC;
   const int K = a.K;
-  rt_lane_angles<double, LPC, APL> ang;
+  // Per-angle arithmetic is done in the intensities' type A (FP32 in the FP32 form, as the
+  // forward source does); every sum over angles and every per-cell quantity stays FP64.
+  using A = T;
+  rt_lane_angles<A, LPC, APL> ang;
   ang.load(a.dirs, a.W, K, l);
   const T *Is = (const T *)a.I_star;
   const T *LI = (const T *)a.lamI;
@@ -41,23 +44,25 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   const double chi = kJ + ks;
 
   // forward recompute (reciprocals instead of divisions; the same root as the forward step)
-  double Gm[APL], iGm[APL], Ico[APL], rr[APL], qv[APL], Iout[APL];
+  const A vA[3] = {(A)v[0], (A)v[1], (A)v[2]}, icA = (A)ic, gamA = (A)gam, yA = (A)y, chiA = (A)chi;
+  const A ychiA = (A)(y * chi);
+  A Gm[APL], iGm[APL], Ico[APL], rr[APL], qv[APL], Iout[APL];
   double sQ = 0, s1 = 0, sG = 0, sI = 0;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double I = ang.ok[q] ? (double)Is[row + ang.k[q]] : 0.0;
-    const double G = gam * (1.0 - (v[0] * ang.dx[q] + v[1] * ang.dy[q] + v[2] * ang.dz[q]) * ic);
-    const double iG = rt_rcp(G);
-    const double G2 = G * G;
+    const A I = ang.ok[q] ? (A)Is[row + ang.k[q]] : A(0);
+    const A G = gamA * (A(1) - (vA[0] * ang.dx[q] + vA[1] * ang.dy[q] + vA[2] * ang.dz[q]) * icA);
+    const A iG = rt_rcp(G);
+    const A G2 = G * G;
     Gm[q] = G;
     iGm[q] = iG;
     Ico[q] = G2 * G2 * I;
-    qv[q] = ang.w[q] * (iG * iG);
-    rr[q] = rt_rcp(1.0 + y * chi * G);
-    sQ += qv[q];
-    s1 += qv[q] * rr[q];
-    sG += qv[q] * G * rr[q];
-    sI += qv[q] * Ico[q] * rr[q];
+    qv[q] = (A)ang.w[q] * (iG * iG);
+    rr[q] = rt_rcp(A(1) + ychiA * G);
+    sQ += (double)qv[q];
+    s1 += (double)(qv[q] * rr[q]);
+    sG += (double)(qv[q] * G * rr[q]);
+    sI += (double)(qv[q] * Ico[q] * rr[q]);
   }
   sQ = rt_group_sum<LPC>(sQ);
   s1 = rt_group_sum<LPC>(s1);
@@ -78,31 +83,33 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   const double planck = a.a_rad * T4 * (1.0 / fourpi);
   const double Jc = (SI + y * kP * SG * planck) * iD;
   const double Ssrc = kP * planck + ks * Jc;
+  const A SsA = (A)Ssrc;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double iG2 = iGm[q] * iGm[q];
-    Iout[q] = (Ico[q] + y * Gm[q] * Ssrc) * rr[q] * (iG2 * iG2);
+    const A iG2 = iGm[q] * iGm[q];
+    Iout[q] = (Ico[q] + yA * Gm[q] * SsA) * rr[q] * (iG2 * iG2);
   }
 
   // reverse
   const double lEp = a.lamE[cell];
   const double lmp[3] = {a.lamM[3 * cell], a.lamM[3 * cell + 1], a.lamM[3 * cell + 2]};
-  double lIn[APL], lGam[APL], lIco[APL], lr[APL], lam[APL];
+  const A lmA[3] = {(A)lmp[0], (A)lmp[1], (A)lmp[2]}, clEA = (A)(c * lEp), icbA = (A)icb;
+  A lIn[APL], lGam[APL], lIco[APL], lr[APL], lam[APL];
   double lS = 0.0;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double iG2 = iGm[q] * iGm[q];
-    const double nl = ang.dx[q] * lmp[0] + ang.dy[q] * lmp[1] + ang.dz[q] * lmp[2];
-    const double through = fourpi * ang.w[q] * ((c * lEp + nl) * icb);
-    const double lin = ang.ok[q] ? (double)LI[row + ang.k[q]] : 0.0;
-    const double ell = lin - through;
+    const A iG2 = iGm[q] * iGm[q];
+    const A nl = ang.dx[q] * lmA[0] + ang.dy[q] * lmA[1] + ang.dz[q] * lmA[2];
+    const A through = (A)(fourpi * ang.w[q]) * ((clEA + nl) * icbA);
+    const A lin = ang.ok[q] ? (A)LI[row + ang.k[q]] : A(0);
+    const A ell = lin - through;
     lam[q] = through;
     lIn[q] = ell * (iG2 * iG2);
-    lGam[q] = -4.0 * ell * Iout[q] * iGm[q];
+    lGam[q] = A(-4) * ell * Iout[q] * iGm[q];
     lIco[q] = lIn[q] * rr[q];
-    lS += lIn[q] * y * Gm[q] * rr[q];
-    lGam[q] += lIn[q] * y * Ssrc * rr[q];
-    lr[q] = lIn[q] * (Ico[q] + y * Gm[q] * Ssrc);
+    lS += (double)(lIn[q] * yA * Gm[q] * rr[q]);
+    lGam[q] += lIn[q] * yA * SsA * rr[q];
+    lr[q] = lIn[q] * (Ico[q] + yA * Gm[q] * SsA);
   }
   lS = rt_group_sum<LPC>(lS);
   double lkP = lS * planck, lkJ = 0.0;
@@ -131,37 +138,39 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   lS1 += lD;
   lkJ += lD * y * SG;
   lSG += lD * y * kJ;
+  const A lS1A = (A)lS1, lSGA = (A)lSG, lSIA = (A)lSI, iQA = (A)iQ;
   double lchi = 0.0, sw = 0.0;
-  double lWt[APL];
+  A lWt[APL];
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double Wt = qv[q] * iQ;
-    lWt[q] = lS1 * rr[q] + lSG * Gm[q] * rr[q] + lSI * Ico[q] * rr[q];
-    lr[q] += lS1 * Wt + lSG * Wt * Gm[q] + lSI * Wt * Ico[q];
-    lGam[q] += lSG * Wt * rr[q];
-    lIco[q] += lSI * Wt * rr[q];
-    const double lden = -lr[q] * rr[q] * rr[q];
-    lchi += lden * y * Gm[q];
-    lGam[q] += lden * y * chi;
-    sw += lWt[q] * Wt;
+    const A Wt = qv[q] * iQA;
+    lWt[q] = lS1A * rr[q] + lSGA * Gm[q] * rr[q] + lSIA * Ico[q] * rr[q];
+    lr[q] += lS1A * Wt + lSGA * Wt * Gm[q] + lSIA * Wt * Ico[q];
+    lGam[q] += lSGA * Wt * rr[q];
+    lIco[q] += lSIA * Wt * rr[q];
+    const A lden = -lr[q] * rr[q] * rr[q];
+    lchi += (double)(lden * yA * Gm[q]);
+    lGam[q] += lden * yA * chiA;
+    sw += (double)(lWt[q] * Wt);
   }
   lchi = rt_group_sum<LPC>(lchi);
   sw = rt_group_sum<LPC>(sw);
   lkJ += lchi;
   const double igam = rt_rcp(gam);
+  const A swA = (A)sw, igamA = (A)igam;
   double lgam = 0.0, lv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double G2 = Gm[q] * Gm[q];
-    const double lq = (lWt[q] - sw) * iQ;
-    lGam[q] += lq * (-2.0 * qv[q] * iGm[q]);
+    const A G2 = Gm[q] * Gm[q];
+    const A lq = (lWt[q] - swA) * iQA;
+    lGam[q] += lq * (A(-2) * qv[q] * iGm[q]);
     lam[q] += lIco[q] * G2 * G2;
-    lGam[q] += lIco[q] * 4.0 * Ico[q] * iGm[q];
-    lgam += lGam[q] * Gm[q] * igam;
-    const double gl = lGam[q] * gam * ic;
-    lv[0] -= gl * ang.dx[q];
-    lv[1] -= gl * ang.dy[q];
-    lv[2] -= gl * ang.dz[q];
+    lGam[q] += lIco[q] * A(4) * Ico[q] * iGm[q];
+    lgam += (double)(lGam[q] * Gm[q] * igamA);
+    const A gl = lGam[q] * gamA * icA;
+    lv[0] -= (double)(gl * ang.dx[q]);
+    lv[1] -= (double)(gl * ang.dy[q]);
+    lv[2] -= (double)(gl * ang.dz[q]);
   }
   lgam = rt_group_sum<LPC>(lgam);
   lv[0] = rt_group_sum<LPC>(lv[0]);
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   T *LS = (T *)a.lam_star;
 #pragma unroll
   for (int q = 0; q < APL; ++q)
-    if (ang.ok[q]) LS[row + ang.k[q]] = (T)(lam[q] * iVp);
+    if (ang.ok[q]) LS[row + ang.k[q]] = (T)((double)lam[q] * iVp);
   if (l == 0) {
     const double g3 = gam * gam * gam * (ic * ic);
     a.lamE[cell] = lE;
