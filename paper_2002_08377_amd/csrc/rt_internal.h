@@ -98,8 +98,9 @@ hipError_t rt_launch_half_faces(rt_mesh *m, const int32_t *face_cells, const dou
 hipError_t rt_launch_volume_rate(rt_mesh *m, hipStream_t s);
 
 // Lane layout of the step kernel for K angles: (lanes per cell << 8) | angles per lane.
-// Antipodal sets with K/2 a multiple of 8 (K/8 in 2..12) or of 4 (K/4 in {2, 6, 10}) use
-// the paired kernel; everything else 16 lanes (K a multiple of 16 or above 64) or 8.
+// Antipodal sets (either order) with K/2 a multiple of 8 (K/8 in 2..12) or of 4 (K/4 in
+// {2, 6, 10}) use the paired kernel; everything else 16 lanes (K a multiple of 16 or above
+// 64) or 8.
 // The paired layout for K, or 0 when the paired kernel has none (the general kernel
 // then serves the set even if it is antipodal).
 static inline int rt_paired_lanes(int K) {
