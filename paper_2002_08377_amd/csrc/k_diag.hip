@@ -170,53 +170,70 @@ __global__ __launch_bounds__(RT_BLOCK) void k_loss(int64_t N, int K, const int32
 // E_r = 4 pi sum W I, F_r = 4 pi c sum W n I, P_r = 4 pi sum W n n I.  The LPC lanes of a
 // cell sum their angles; the group sums (DPP) leave the totals in every lane, and lane c
 // writes component c (two rounds when LPC = 8), so a cell's 80 bytes go out together.
+// Each lane group takes RT_MOM_CELLS cells (CPB apart, so every round of a workgroup reads
+// consecutive rows): the lane's directions and weights are loaded once for all of them,
+// and all their intensity loads are issued before any is used.
+#define RT_MOM_CELLS 4
 template <typename T, int LPC, int APL>
 __global__ __launch_bounds__(RT_BLOCK) void k_moments(int64_t N, int K, const double *dirs, const double *W,
                                                       double c_light, const T *I, double *out, int64_t nblk) {
   const int64_t lb = rt_logical_block(nblk);
   if (lb < 0) return;
   constexpr int CPB = RT_BLOCK / LPC;
-  const int64_t cell = lb * CPB + threadIdx.x / LPC;
-  if (cell >= N) return;  // whole lane groups
+  constexpr int R = RT_MOM_CELLS;
+  const int64_t c0 = lb * CPB * R + threadIdx.x / LPC;
+  if (c0 >= N) return;  // whole lane groups
   const int l = threadIdx.x % LPC;
   rt_lane_angles<double, LPC, APL> ang;
   ang.load(dirs, W, K, l);
-  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T x[R][APL];
 #pragma unroll
-  for (int q = 0; q < APL; ++q) {
-    const double wI = ang.ok[q] ? ang.w[q] * (double)I[cell * (int64_t)K + ang.k[q]] : 0.0;
-    const double nx = ang.dx[q], ny = ang.dy[q], nz = ang.dz[q];
-    m[0] += wI;
-    m[1] += wI * nx;
-    m[2] += wI * ny;
-    m[3] += wI * nz;
-    m[4] += wI * nx * nx;
-    m[5] += wI * ny * ny;
-    m[6] += wI * nz * nz;
-    m[7] += wI * nx * ny;
-    m[8] += wI * nx * nz;
-    m[9] += wI * ny * nz;
+  for (int r = 0; r < R; ++r) {
+    const int64_t cell = c0 + (int64_t)CPB * r;
+#pragma unroll
+    for (int q = 0; q < APL; ++q) x[r][q] = cell < N && ang.ok[q] ? I[cell * (int64_t)K + ang.k[q]] : T(0);
   }
   const double fourpi = 4.0 * RT_PI;
-  double r[10];
 #pragma unroll
-  for (int c = 0; c < 10; ++c) r[c] = rt_group_sum<LPC>(m[c]) * (c >= 1 && c <= 3 ? fourpi * c_light : fourpi);
+  for (int r = 0; r < R; ++r) {
+    const int64_t cell = c0 + (int64_t)CPB * r;
+    if (cell >= N) break;  // the same for all lanes of the group
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-  for (int c0 = 0; c0 < 10; c0 += LPC) {
-    // lane l writes component c0 + l
-    double v = r[c0];
+    for (int q = 0; q < APL; ++q) {
+      const double wI = ang.w[q] * (double)x[r][q];
+      const double nx = ang.dx[q], ny = ang.dy[q], nz = ang.dz[q];
+      m[0] += wI;
+      m[1] += wI * nx;
+      m[2] += wI * ny;
+      m[3] += wI * nz;
+      m[4] += wI * nx * nx;
+      m[5] += wI * ny * ny;
+      m[6] += wI * nz * nz;
+      m[7] += wI * nx * ny;
+      m[8] += wI * nx * nz;
+      m[9] += wI * ny * nz;
+    }
+    double v[10];
 #pragma unroll
-    for (int c = c0 + 1; c < c0 + LPC && c < 10; ++c)
-      if (l == c - c0) v = r[c];
-    if (c0 + l < 10) out[10 * cell + c0 + l] = v;
+    for (int c = 0; c < 10; ++c) v[c] = rt_group_sum<LPC>(m[c]) * (c >= 1 && c <= 3 ? fourpi * c_light : fourpi);
+#pragma unroll
+    for (int b = 0; b < 10; b += LPC) {
+      // lane l writes component b + l
+      double o = v[b];
+#pragma unroll
+      for (int c = b + 1; c < b + LPC && c < 10; ++c)
+        if (l == c - b) o = v[c];
+      if (b + l < 10) out[10 * cell + b + l] = o;
+    }
   }
 }
 
 template <typename T, int LPC, int APL>
 hipError_t launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
                           double *out, hipStream_t s) {
-  const int64_t cpb = RT_BLOCK / LPC;
-  const int64_t nblk = (m->N + cpb - 1) / cpb;
+  const int64_t cpc = (int64_t)(RT_BLOCK / LPC) * RT_MOM_CELLS;  // cells per workgroup
+  const int64_t nblk = (m->N + cpc - 1) / cpc;
   hipLaunchKernelGGL((k_moments<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K,
                      dirs, W, c_light, (const T *)I, out, nblk);
   return hipGetLastError();
