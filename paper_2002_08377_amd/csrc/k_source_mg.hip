@@ -41,9 +41,9 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   const double gam = rsqrt(1.0 - (vx * vx + vy * vy + vz * vz) * (ic * ic));
   const double y = a.dt * a.c_red * rho;
   const T tg = (T)gam, tvx = (T)(vx * ic), tvy = (T)(vy * ic), tvz = (T)(vz * ic);
-  // group-independent per angle: Gamma, 1/Gamma^2 and the comoving weight
+  // group-independent per angle: Gamma and 1/Gamma^2 (the comoving weight W / Gamma^2 is
+  // formed again where it is used, which holds fewer registers than keeping it)
   T Gm[APL], iG2[APL];
-  double qk[APL];
   double sQ = 0;
 #pragma unroll
   for (int q = 0; q < P; ++q) {
@@ -55,28 +55,45 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   for (int q = 0; q < APL; ++q) {
     const T iG = rt_rcp(Gm[q]);
     iG2[q] = iG * iG;
-    qk[q] = ang.wt(q) * (double)iG2[q];
-    sQ += qk[q];
+    sQ += ang.wt(q) * (double)iG2[q];
   }
   sQ = rt_group_sum<LPC>(sQ);
   const double iQ = rt_rcp(sQ);
 
-  // pass 1: per-group comoving sums and the quartic's coefficients
-  double Asum = 0, Csum = 0;
-  for (int j = 0; j < G; ++j) {
+  // A group's row and opacities, loaded one group ahead in both passes so that their
+  // memory latency overlaps the previous group's arithmetic.
+  struct grp {
+    T I[APL];
+    double kJ, ks, kP;
+  };
+  auto fetch = [&](int j, grp &o) {
     const int64_t gc = (int64_t)j * N + cell;
     const T *Ir = (const T *)a.I + gc * K;
-    const double kJ = a.kJ[gc], ks = a.ks[gc], kP = a.kP[gc];
+#pragma unroll
+    for (int q = 0; q < APL; ++q) o.I[q] = Ir[ang.k[q]];
+    o.kJ = a.kJ[gc];
+    o.ks = a.ks[gc];
+    o.kP = a.kP[gc];
+  };
+
+  // pass 1: per-group comoving sums and the quartic's coefficients
+  double Asum = 0, Csum = 0;
+  grp cur, nxt;
+  fetch(0, cur);
+  for (int j = 0; j < G; ++j) {
+    if (j + 1 < G) fetch(j + 1, nxt);
+    const double kJ = cur.kJ, ks = cur.ks, kP = cur.kP;
     const T tyc = (T)(y * (kJ + ks));
     double s1 = 0, sG = 0, sI = 0;
 #pragma unroll
     for (int q = 0; q < APL; ++q) {
-      const T I = Ir[ang.k[q]];
+      const T I = cur.I[q];
       const T r = rt_rcp(T(1) + tyc * Gm[q]);
       const T G2 = Gm[q] * Gm[q];
-      s1 += qk[q] * (double)r;
-      sG += qk[q] * (double)(Gm[q] * r);
-      sI += qk[q] * (double)(G2 * G2 * I * r);
+      const double qk = ang.wt(q) * (double)iG2[q];
+      s1 += qk * (double)r;
+      sG += qk * (double)(Gm[q] * r);
+      sI += qk * (double)(G2 * G2 * I * r);
     }
     s1 = rt_group_sum<LPC>(s1) * iQ;
     sG = rt_group_sum<LPC>(sG) * iQ;
@@ -90,6 +107,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
       sg[4 * j + 2] = sI;
       sg[4 * j + 3] = iD;
     }
+    cur = nxt;
   }
   const double rcv = rho * a.cv;
   const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * irho) * rt_rcp(rcv);
@@ -103,10 +121,13 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
 
   // pass 2: per group, update the row and book the energy and momentum handed over
   double dE = 0, dFx = 0, dFy = 0, dFz = 0;
+  fetch(0, cur);
   for (int j = 0; j < G; ++j) {
-    const int64_t gc = (int64_t)j * N + cell;
-    T *Ir = (T *)a.I + gc * K;
-    const double kJ = a.kJ[gc], ks = a.ks[gc], kP = a.kP[gc];
+    // the next group's row is another array than this group's, so reading it ahead of
+    // this group's stores is safe
+    if (j + 1 < G) fetch(j + 1, nxt);
+    T *Ir = (T *)a.I + ((int64_t)j * N + cell) * K;
+    const double kJ = cur.kJ, ks = cur.ks, kP = cur.kP;
     const T tyc = (T)(y * (kJ + ks));
     const double Jc = (sg[4 * j + 2] + y * kP * sg[4 * j + 1] * planck) * sg[4 * j + 3];
     const T ySrc = (T)(y * (kP * planck + ks * Jc));
@@ -114,7 +135,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       auto upd = [&](int qq) -> double {
-        const T I0 = Ir[ang.k[qq]];
+        const T I0 = cur.I[qq];
         const T r = rt_rcp(T(1) + tyc * Gm[qq]);
         const T out = I0 * r + r * iG2[qq] * rt_rcp(Gm[qq]) * ySrc;
         if (ang.ok[qq]) Ir[ang.k[qq]] = out;
@@ -131,6 +152,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
       dFy += wd * (double)ang.y[q];
       dFz += wd * (double)ang.z[q];
     }
+    cur = nxt;
   }
   dE = rt_group_sum<LPC>(dE);
   dFx = rt_group_sum<LPC>(dFx);
