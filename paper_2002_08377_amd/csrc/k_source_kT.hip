@@ -18,8 +18,14 @@ struct kT_eval {
   double kP, kJ, S1, SG, SI, D, f, fp;
 };
 
+// Left to itself the compiler gives the larger paired instantiations all 256 registers plus
+// accumulation registers, one wave per SIMD; held to two waves the 10-angle ones spill 160
+// bytes per lane and still run faster (128^3 x 80: 3.09 -> 2.78 ms FP32, 3.20 -> 3.09 ms
+// FP64).  The other layouts keep the compiler's choice.
+template <int APL, int PAIRED> struct rt_kT_waves { static constexpr int value = PAIRED && APL <= 10 ? 2 : 1; };
 template <typename T, int LPC, int APL, bool FULL, int PAIRED>
-__global__ __launch_bounds__(RT_BLOCK) void k_source_kT(rt_kT_args a, int64_t nblk) {
+__global__ __launch_bounds__(RT_BLOCK) __attribute__((amdgpu_waves_per_eu(rt_kT_waves<APL, PAIRED>::value))) void
+k_source_kT(rt_kT_args a, int64_t nblk) {
   using Ang = rt_step_angles<double, LPC, APL, FULL, PAIRED>;
   constexpr int CPB = RT_BLOCK / LPC;
   const int64_t lb = rt_logical_block(nblk);
