@@ -31,10 +31,12 @@ static inline int64_t rt_grid_for(int64_t nblk) { return ((nblk + 7) / 8) * 8; }
 // halves moved by v_mov_dpp; no LDS round trip).  Controls used below (gfx9 encodings):
 // quad_perm [1,0,3,2] = lane ^ 1, quad_perm [2,3,0,1] = lane ^ 2, row_half_mirror =
 // lane 7 - i within each 8, row_mirror = lane 15 - i within each 16.
+// Every source lane of these patterns is an active lane of the same group, so no lane
+// keeps an old value and the move needs no initialised destination.
 template <int CTRL> __device__ __forceinline__ double rt_dpp(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
