@@ -8,9 +8,13 @@
 namespace {
 
 // Faces gathered per batch: all their neighbour-row loads are issued before any is
-// used, so one memory round trip serves U faces (two faces measured ~2% faster than
-// four in FP32 at 80 angles).
-template <typename T> struct rt_batch { static constexpr int U = 2; };
+// used, so one memory round trip serves U faces.  At 128^3 x 80: two faces measured ~2%
+// faster than four in FP32; the FP64 form with antipodes side by side (one 16-byte load
+// per angle pair, two waves per SIMD) runs 5% faster with three (1.91 against 2.00 ms;
+// four: 1.99).
+template <typename T, int PAIRED> struct rt_batch {
+  static constexpr int U = PAIRED == 2 && sizeof(T) == 8 ? 3 : 2;
+};
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
 // transport of PLM stage 2 (+ source); 3: the transpose of upwind transport (the
@@ -26,7 +30,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk)
   using V4 = typename rt_vec4<T>::type;
   using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED>;
   constexpr int P = Ang::P;
-  constexpr int U = rt_batch<T>::U;
+  constexpr int U = rt_batch<T, PAIRED>::U;
   constexpr int CPB = RT_BLOCK / LPC;
   extern __shared__ __align__(16) unsigned char rt_smem[];
   V4 *s_an = (V4 *)rt_smem;
