@@ -38,6 +38,24 @@ def test_angle_set_s4_mu1():
     assert abs(np.min(np.abs(d)) - 0.3500212) < 1e-7
 
 
+@pytest.mark.parametrize("K", [8, 24, 48, 80, 120])
+def test_adjacent_pair_order(K):
+    """The reordering puts each antipode right after its angle and keeps the weights with
+    their directions; the problem's intensity columns follow the same permutation."""
+    d, w = inp.angle_set(K)
+    perm = inp.adjacent_pair_order(K)
+    assert sorted(perm.tolist()) == list(range(K))
+    da, wa = d[perm], w[perm]
+    assert np.array_equal(da[1::2], -da[0::2]) and np.array_equal(wa[1::2], wa[0::2])
+    p = inp.make_problem(0, n=6, K=K, steps=1)
+    q = inp.with_angle_order(p, perm)
+    assert np.array_equal(q.dirs, p.dirs[perm]) and np.array_equal(q.weights, p.weights[perm])
+    assert np.array_equal(q.state.I, p.state.I[:, perm]) and q.state.I.flags["C_CONTIGUOUS"]
+    assert np.array_equal(q.state.etot, p.state.etot) and q.mesh is p.mesh
+    with pytest.raises(ValueError):
+        inp.adjacent_pair_order(7)
+
+
 @pytest.mark.parametrize("n,jitter", [(6, 0.2), (8, 0.2), (12, 0.2), (7, 0.05)])
 def test_voronoi_invariants(n, jitter):
     m = inp.voronoi_mesh(n, jitter, seed=11)
