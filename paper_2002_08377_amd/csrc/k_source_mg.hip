@@ -63,7 +63,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   // A group's row (and in the FP64 form its opacities) is loaded one group ahead in both
   // passes, so that its memory latency overlaps the previous group's arithmetic.  The FP32
   // form loads the opacities at the top of each group instead: held ahead, their registers
-  // would cost a wave per SIMD (174 registers against 160; 1.82 against 1.72 ms at 128^3 x 80,
+  // would cost a wave per SIMD (174 registers against 160; 1.82 against 1.70 ms at 128^3 x 80,
   // 4 groups), while the FP64 form is 3% faster with them ahead.
   constexpr bool KAPPA_AHEAD = sizeof(T) == 8;
   struct grp {
@@ -98,6 +98,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   double Asum = 0, Csum = 0;
   grp cur, nxt;
   fetch(0, cur);
+  nxt = cur;  // defined when the last group rotates it in
   for (int j = 0; j < G; ++j) {
     if (j + 1 < G) fetch(j + 1, nxt);
     double kJ, ks, kP;
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   // pass 2: per group, update the row and book the energy and momentum handed over
   double dE = 0, dFx = 0, dFy = 0, dFz = 0;
   fetch(0, cur);
+  nxt = cur;
   for (int j = 0; j < G; ++j) {
     // the next group's row is another array than this group's, so reading it ahead of
     // this group's stores is safe
