@@ -42,31 +42,36 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
   const double m0 = a.mom[3 * cell], m1 = a.mom[3 * cell + 1], m2 = a.mom[3 * cell + 2];
   const double Eg = a.etot[cell];
   const double c = a.c_light, fourpi = 4.0 * RT_PI;
-  const double vx = m0 / rho, vy = m1 / rho, vz = m2 / rho;
-  const double gam = 1.0 / sqrt(1.0 - (vx * vx + vy * vy + vz * vz) / (c * c));
+  // reciprocals (within an ulp) and products instead of FP64 divisions
+  const double irho = rt_rcp(rho), ic = rt_rcp(c);
+  const double vx = m0 * irho, vy = m1 * irho, vz = m2 * irho;
+  const double gam = rsqrt(1.0 - (vx * vx + vy * vy + vz * vz) * (ic * ic));
   double Gm[APL], Wt[APL], Ic[APL];
   double norm = 0.0;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
     const double I0 = (double)Ir[ang.k[q]];
     const double vn = vx * ang.dx(q) + vy * ang.dy(q) + vz * ang.dz(q);
-    Gm[q] = gam * (1.0 - vn / c);
+    Gm[q] = gam * (1.0 - vn * ic);
     const double G2 = Gm[q] * Gm[q];
+    const double iG = rt_rcp(Gm[q]);
     Ic[q] = G2 * G2 * I0;
-    Wt[q] = ang.wt(q) / G2;
+    Wt[q] = ang.wt(q) * (iG * iG);
     norm += Wt[q];
   }
   norm = rt_group_sum<LPC>(norm);
+  const double inorm = rt_rcp(norm);
 #pragma unroll
-  for (int q = 0; q < APL; ++q) Wt[q] /= norm;
+  for (int q = 0; q < APL; ++q) Wt[q] *= inorm;
   const double y = a.dt * a.c_red * rho;
   const double rcv = rho * a.cv;
-  const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho) / rcv;
+  const double Tn = (Eg - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * irho) * rt_rcp(rcv);
+  const double iTref = rt_rcp(a.T_ref);
   const double kP0 = a.kP0[cell], kJ0 = a.kJ0[cell], ks = a.ks[cell];
 
   auto evaluate = [&](double Tq) {
     kT_eval e;
-    const double tr = Tq / a.T_ref;
+    const double tr = Tq * iTref;
     const double pP = pow(tr, a.bP);
     e.kP = kP0 * pP;
     e.kJ = kJ0 * (a.bJ == a.bP ? pP : pow(tr, a.bJ));
@@ -91,13 +96,14 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
     e.D = e.S1 + y * e.kJ * e.SG;
     const double T3 = Tq * Tq * Tq, T4 = T3 * Tq;
     const double Nn = e.kP * a.a_rad * T4 * e.S1 - fourpi * e.kJ * e.SI;
-    e.f = rcv * (Tq - Tn) + a.dt * c * rho * Nn / e.D;
-    const double dkP = a.bP * e.kP / Tq, dkJ = a.bJ * e.kJ / Tq;
+    const double iD = rt_rcp(e.D), iTq = rt_rcp(Tq);
+    e.f = rcv * (Tq - Tn) + a.dt * c * rho * Nn * iD;
+    const double dkP = a.bP * e.kP * iTq, dkJ = a.bJ * e.kJ * iTq;
     const double dS1 = -y * p1 * dkJ, dSG = -y * pG * dkJ, dSI = -y * pI * dkJ;
     const double dD = dS1 + y * (dkJ * e.SG + e.kJ * dSG);
     const double dN = dkP * a.a_rad * T4 * e.S1 + e.kP * a.a_rad * 4.0 * T3 * e.S1 + e.kP * a.a_rad * T4 * dS1 -
                       fourpi * (dkJ * e.SI + e.kJ * dSI);
-    e.fp = rcv + a.dt * c * rho * (dN * e.D - Nn * dD) / (e.D * e.D);
+    e.fp = rcv + a.dt * c * rho * (dN * e.D - Nn * dD) * (iD * iD);
     return e;
   };
 
@@ -139,7 +145,7 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
     if (e.f == 0.0) break;
     if (e.f < 0.0) lo = Tq;
     else hi = Tq;
-    double Tx = Tq - e.f / e.fp;
+    double Tx = Tq - e.f * rt_rcp(e.fp);
     // a step within the tolerance has converged and is taken as it is; a larger one that
     // leaves the bracket is replaced by bisection
     done = fabs(Tx - Tq) <= 1e-14 * Tq;
@@ -148,15 +154,16 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
   }
 
   const double T4 = Tq * Tq * Tq * Tq;
-  const double planck = a.a_rad * T4 / fourpi;
-  const double Jc = (e.SI + y * e.kP * e.SG * planck) / e.D;
+  const double planck = a.a_rad * T4 * (1.0 / fourpi);
+  const double Jc = (e.SI + y * e.kP * e.SG * planck) * rt_rcp(e.D);
   const double chi = e.kJ + ks;
   double dE = 0, dFx = 0, dFy = 0, dFz = 0;
 #pragma unroll
   for (int q = 0; q < APL; ++q) {
-    const double Inew = (Ic[q] + y * Gm[q] * (e.kP * planck + ks * Jc)) / (1.0 + y * chi * Gm[q]);
-    const double G2 = Gm[q] * Gm[q];
-    const T out = (T)(Inew / (G2 * G2));
+    const double Inew = (Ic[q] + y * Gm[q] * (e.kP * planck + ks * Jc)) * rt_rcp(1.0 + y * chi * Gm[q]);
+    const double iG = rt_rcp(Gm[q]);
+    const double iG2 = iG * iG;
+    const T out = (T)(Inew * (iG2 * iG2));
     // the incoming value is read again here rather than held through the iteration
     const double wd = ang.wt(q) * ((double)Ir[ang.k[q]] - (double)out);
     if (ang.ok[q]) Ir[ang.k[q]] = out;
