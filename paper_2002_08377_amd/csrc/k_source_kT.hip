@@ -71,10 +71,14 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
 
   auto evaluate = [&](double Tq) {
     kT_eval e;
-    const double tr = Tq * iTref;
-    const double pP = pow(tr, a.bP);
+    // (T/T_ref)^b as exp(b ln(T/T_ref)): within (|b ln(T/T_ref)| + 2) ulp, and far cheaper
+    // than pow (whose code alone, even on a branch not taken, costs this kernel registers).
+    // The error stays below the Newton stopping tolerance (1e-14 T) while |b ln| < ~40;
+    // beyond that the bracketed iteration still ends, through its bisection steps.
+    const double lt = log(Tq * iTref);
+    const double pP = exp(a.bP * lt);
     e.kP = kP0 * pP;
-    e.kJ = kJ0 * (a.bJ == a.bP ? pP : pow(tr, a.bJ));
+    e.kJ = kJ0 * (a.bJ == a.bP ? pP : exp(a.bJ * lt));
     const double chi = e.kJ + ks;
     double s1 = 0, sG = 0, sI = 0, p1 = 0, pG = 0, pI = 0;
 #pragma unroll

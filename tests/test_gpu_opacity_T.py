@@ -57,6 +57,29 @@ def test_source_kT_matches_oracle(dtype, K, bP, bJ, layout):
     mesh.free()
 
 
+@pytest.mark.parametrize("b,Tr", [(20.0, 0.1), (-20.0, 10.0)])
+def test_source_kT_extreme_laws_match_oracle(b, Tr):
+    """The largest allowed exponents with T / T_ref far from one (|b ln(T/T_ref)| up to 60,
+    where the kernel's exp(b ln) power law is least exact): the iteration still ends and
+    matches the oracle's pow-based root to 1e-12 (FP64)."""
+    K = 24
+    p = inp.make_problem(0, n=7, K=K, steps=1)
+    st, ph = p.state, p.phys
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, rt.F64)
+    I, mom, etot = _d(st.I), _d(st.mom), _d(st.etot)
+    T = torch.zeros(p.mesh.n_cells, dtype=torch.float64, device="cuda")
+    rt.source_implicit_kT(mesh, prm, ang, I, _d(st.rho), mom, etot, _d(st.kP), _d(st.kJ), _d(st.ks), Tr, b, b, T)
+    torch.cuda.synchronize()
+    Io, mo, eo, To = orc.source_kT(p.dirs, p.weights, ph, p.dt, st.I, st.rho, st.mom, st.etot, st.kP, st.kJ, st.ks,
+                                   Tr, b, b)
+    assert rel_err(I.cpu().numpy(), Io) < 1e-12
+    assert rel_err(T.cpu().numpy(), To) < 1e-12
+    assert rel_err(etot.cpu().numpy(), eo) < 1e-12
+    mesh.free()
+
+
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 def test_step_kT_matches_oracle(dtype):
     K, bP, bJ, Tr = 48, -3.5, -3.5, 1.0
