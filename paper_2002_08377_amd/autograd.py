@@ -46,6 +46,12 @@ class RTSystem:
             raise ValueError("the mesh must be uploaded with MESH_ADJOINT")
 
 
+def _gas_views(gas):
+    """Volume [N], momentum [N, 3] and gas energy [N]: contiguous views of one [5 N] buffer."""
+    N = gas.shape[0] // 5
+    return gas[:N], gas[N:4 * N].view(N, 3), gas[4 * N:]
+
+
 class RTSteps(torch.autograd.Function):
     """(I^0, kappa_a, E_g^0, (rho v)^0) -> (I^S, E_g^S, (rho v)^S) after n_steps steps.
 
@@ -61,18 +67,22 @@ class RTSteps(torch.autograd.Function):
         I = I0.detach().to(td).contiguous().clone()
         I2 = torch.empty_like(I)
         kap = kappa_a.detach().contiguous()
-        etot = etot0.detach().contiguous().clone()
-        mom = mom0.detach().contiguous().clone()
-        vol = system.vol0.detach().contiguous().clone()
+        # volume, momentum and gas energy live in one buffer, so that a checkpoint or a tape
+        # record of them is a single copy
+        gas = torch.empty(5 * I.shape[0], dtype=torch.float64, device=I.device)
+        vol, mom, etot = _gas_views(gas)
+        vol.copy_(system.vol0.detach())
+        mom.copy_(mom0.detach())
+        etot.copy_(etot0.detach())
         ckpts = []
         last = ((n_steps - 1) // ckpt_every) * ckpt_every if n_steps else 0  # first step of the last segment
         tape = []
         for n in range(n_steps):
             if n % ckpt_every == 0:
-                ckpts.append((I.clone(), etot.clone(), mom.clone(), vol.clone()))
+                ckpts.append((I.clone(), gas.clone()))
             if n >= last:
                 # the last segment: tape it now (the taped step gives the fused step's values)
-                rec = (torch.empty_like(I), vol.clone(), mom.clone(), etot.clone())
+                rec = (torch.empty_like(I), gas.clone())
                 rt.step_taped(system.mesh, system.params, system.angles, I, I2, rec[0], vol, system.rho, mom, etot,
                               kap, kap, system.ks)
                 tape.append(rec)
@@ -87,7 +97,7 @@ class RTSteps(torch.autograd.Function):
         ctx.last_tape = tape
         ctx.save_for_backward(kap)
         ctx.in_dtype = I0.dtype
-        return I, etot, mom
+        return I, etot.clone(), mom.clone()
 
     @staticmethod
     def backward(ctx, gI, gE, gM):
@@ -113,17 +123,20 @@ class RTSteps(torch.autograd.Function):
             if seg == len(ctx.ckpts) - 1:
                 tape = ctx.last_tape  # taped by the forward pass
             else:
-                I, etot, mom, vol = (t.clone() for t in ctx.ckpts[seg])
+                # each checkpoint is read once, so the recompute steps in its own buffers
+                I, gas = ctx.ckpts[seg]
+                vol, mom, etot = _gas_views(gas)
                 n0 = seg * L
                 nseg = min(L, ctx.n_steps - n0)
                 tape = []
                 for n in range(nseg):
-                    vol_n, mom_n, etot_n = vol.clone(), mom.clone(), etot.clone()
+                    gas_n = gas.clone()
                     rt.step_taped(s.mesh, s.params, s.angles, I, I2, tape_I[n], vol, s.rho, mom, etot, kap, kap,
                                   s.ks)
                     I, I2 = I2, I
-                    tape.append((tape_I[n], vol_n, mom_n, etot_n))
-            for I_star, vol_n, mom_n, etot_n in reversed(tape):
+                    tape.append((tape_I[n], gas_n))
+            for I_star, gas_n in reversed(tape):
+                vol_n, mom_n, etot_n = _gas_views(gas_n)
                 rt.step_adjoint(s.mesh, s.params, s.angles, I_star, vol_n, s.rho, mom_n, etot_n, kap, kap, s.ks,
                                 lamI, lamE, lamM, dk, dk)
         ctx.ckpts = None
