@@ -152,19 +152,15 @@ class FluxLoss(torch.autograd.Function):
     def forward(ctx, I, face_weight, system: RTSystem):
         loss = torch.zeros(1, dtype=torch.float64, device=I.device)
         Ic = I.detach().contiguous()
-        rt.flux_loss(system.mesh, system.params, system.angles, Ic, face_weight, loss)
-        ctx.system = system
-        ctx.face_weight = face_weight
-        ctx.shape, ctx.dtype, ctx.device = Ic.shape, Ic.dtype, Ic.device
-        ctx.Ic = Ic
+        # when I needs a gradient the same launch writes the seed dL/dI, kept for backward
+        seed = torch.zeros_like(Ic) if ctx.needs_input_grad[0] else None
+        rt.flux_loss(system.mesh, system.params, system.angles, Ic, face_weight, loss, seed)
+        ctx.seed = seed
         return loss[0]
 
     @staticmethod
     def backward(ctx, g):
-        seed = torch.zeros(ctx.shape, dtype=ctx.dtype, device=ctx.device)
-        rt.flux_loss(ctx.system.mesh, ctx.system.params, ctx.system.angles, ctx.Ic, ctx.face_weight,
-                     torch.zeros(1, dtype=torch.float64, device=ctx.device), seed)
-        return seed * g.to(ctx.dtype), None, None
+        return ctx.seed * g.to(ctx.seed.dtype), None, None
 
 
 def rt_steps(I0, kappa_a, etot0, mom0, system: RTSystem, n_steps: int, ckpt_every: int = 8):
