@@ -136,25 +136,35 @@ __global__ __launch_bounds__(RT_BLOCK) void k_loss(int64_t N, int K, const int32
     ang.load(dirs, W, K, l);
     const int64_t row = cell * (int64_t)K;
     double sd[APL], Iv[APL];
-    for (int q = 0; q < APL; ++q) {
-      sd[q] = 0.0;
-      Iv[q] = ang.ok[q] ? (double)I[row + ang.k[q]] : 0.0;
-    }
+    for (int q = 0; q < APL; ++q) sd[q] = Iv[q] = 0.0;
+    bool have_row = false;  // the row is read only by cells with a weighted face (few)
     const double fpc = 4.0 * RT_PI * c_light;
     double part = 0.0;
-    for (int h = row_ptr[cell]; h < row_ptr[cell + 1]; ++h) {
-      const int32_t fc = hf_face[h];
-      const int64_t f = fc >= 0 ? fc : -(int64_t)fc - 1;
-      const double u = face_weight[f];
-      if (u == 0.0) continue;
-      const double sg = fc >= 0 ? u : -u;
-      const double4 r = hf_an[h];
-      for (int q = 0; q < APL; ++q) {
-        const double m = r.x * ang.dx[q] + r.y * ang.dy[q] + r.z * ang.dz[q];
-        if (m > 0.0) {
-          const double coef = sg * fpc * ang.w[q] * m;
-          part += coef * Iv[q];
-          sd[q] += coef;
+    const int h0 = row_ptr[cell], h1 = row_ptr[cell + 1];
+    constexpr int B = 4;  // faces whose ids and weights are fetched together
+    for (int hb = h0; hb < h1; hb += B) {
+      int32_t fc[B];
+      double u[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) fc[b] = hb + b < h1 ? hf_face[hb + b] : 0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) u[b] = hb + b < h1 ? face_weight[fc[b] >= 0 ? fc[b] : -(int64_t)fc[b] - 1] : 0.0;
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (u[b] == 0.0) continue;
+        if (!have_row) {
+          for (int q = 0; q < APL; ++q) Iv[q] = ang.ok[q] ? (double)I[row + ang.k[q]] : 0.0;
+          have_row = true;
+        }
+        const double sg = fc[b] >= 0 ? u[b] : -u[b];
+        const double4 r = hf_an[hb + b];
+        for (int q = 0; q < APL; ++q) {
+          const double m = r.x * ang.dx[q] + r.y * ang.dy[q] + r.z * ang.dz[q];
+          if (m > 0.0) {
+            const double coef = sg * fpc * ang.w[q] * m;
+            part += coef * Iv[q];
+            sd[q] += coef;
+          }
         }
       }
     }
