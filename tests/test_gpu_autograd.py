@@ -128,6 +128,22 @@ def test_taped_step_rejects_overlap_and_plm():
                       x["mom"].clone(), x["etot"].clone(), x["kap"], x["kap"], system.ks)
 
 
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_zero_steps_is_the_identity(dtype):
+    """No steps: the outputs are the inputs and the gradients pass straight through."""
+    p = inp.make_problem(0, n=6, K=24, steps=1)
+    system, x = _system(p, dtype)
+    td = rt.torch_dtype(dtype)
+    I0 = x["I0"].to(td).clone().requires_grad_()
+    kap, etot, mom = (x[k].clone().requires_grad_() for k in ("kap", "etot", "mom"))
+    IS, ES, MS = rt_steps(I0, kap, etot, mom, system, 0, 8)
+    assert torch.equal(IS, I0.detach()) and torch.equal(ES, etot.detach()) and torch.equal(MS, mom.detach())
+    (2.0 * IS.sum() + 3.0 * ES.sum() + 4.0 * MS.sum()).backward()
+    assert torch.all(I0.grad == 2.0) and torch.all(etot.grad == 3.0) and torch.all(mom.grad == 4.0)
+    assert torch.all(kap.grad == 0.0)
+    system.mesh.free()
+
+
 def test_gradient_matches_oracle():
     p = inp.make_problem(2, n=8, K=24, steps=5)
     st = p.state
