@@ -25,8 +25,16 @@ template <typename T, int PAIRED> struct rt_batch {
 // The cells of a workgroup are consecutive, so their half-faces form one contiguous
 // range; it is staged in LDS (dynamic size: the largest range of any workgroup,
 // found at upload) and the face loops read their records from there.
+// Occupancy target: the FP64 PLM stage 2 (four rows gathered per face) would take all 256
+// registers at one wave per SIMD; held to two it spills ~130 bytes per lane and runs 5%
+// faster with antipodes K/2 apart (64^3 x 80 PLM step 1.96 -> 1.87 ms; unchanged with them
+// side by side).  Everything else keeps the compiler's choice.
+template <typename T, int MODE> struct rt_step_waves {
+  static constexpr int value = MODE == 2 && sizeof(T) == 8 ? 2 : 1;
+};
 template <typename T, int LPC, int APL, int MODE, bool FULL, int PAIRED>
-__global__ __launch_bounds__(RT_BLOCK) void k_step(rt_step_args a, int64_t nblk) {
+__global__ __launch_bounds__(RT_BLOCK) __attribute__((amdgpu_waves_per_eu(rt_step_waves<T, MODE>::value))) void
+k_step(rt_step_args a, int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
   using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED>;
   constexpr int P = Ang::P;
