@@ -376,6 +376,27 @@ def test_plm_64c_80a_100_steps_energy_drift(dtype):
     assert d1[9] == 0 and d1[8] > 0
 
 
+@pytest.mark.parametrize("scheme", [rt.UPWIND1, rt.PLM_VL2])
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_antipode_orders_step_identically(dtype, scheme):
+    """Storing each antipode K/2 after its angle or right beside it is a layout choice only:
+    each lane holds the same pair of angles in both orders and every sum runs in the same
+    order, so four steps give the same bits once the angles are put back in one order."""
+    p = _prob(1, n=9, K=48, steps=4)
+    perm = inp.adjacent_pair_order(48)
+    runs = []
+    for q in (p, inp.with_angle_order(p, perm)):
+        dp = DeviceProblem(q, dtype=dtype, scheme=scheme)
+        dp.run_gpu(4)
+        torch.cuda.synchronize()
+        runs.append(dp)
+    a, b = runs
+    assert a.angles.layout == rt.ANGLES_ANTIPODAL and b.angles.layout == rt.ANGLES_ANTIPODAL_ADJACENT
+    assert np.array_equal(a.host(a.I)[:, perm], b.host(b.I))
+    for name in ("T", "etot", "mom", "vol"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+
+
 def test_antipodal_set_without_paired_layout_uses_general_kernel():
     """K = 12 antipodal directions (6 and their opposites): the paired kernel has no layout
     for K = 12, so the general kernel must serve it; one step matches the oracle."""
