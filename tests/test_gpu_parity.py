@@ -174,11 +174,13 @@ def test_plm_transport_only_matches_oracle():
     assert rel_err(dp.host(dp.I2), so.I) < 1e-12
 
 
-@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_plm_64c_80a_one_step(dtype):
-    """The PLM workload's full size (64^3 cells, 80 angles), one step."""
-    p = inp.make_problem(1, steps=1)
+@pytest.mark.parametrize("dtype,order", [(rt.F64, "half"), (rt.F32, "half"), (rt.F64, ADJ)])
+def test_plm_64c_80a_one_step(dtype, order):
+    """The PLM workload's full size (64^3 cells, 80 angles), one step, also in the order the
+    FP64 form is timed in (antipodes side by side; compared in that order)."""
+    p, _ = _with_layout(inp.make_problem(1, steps=1), ADJ if order == ADJ else None)
     dp = DeviceProblem(p, dtype=dtype, scheme=rt.PLM_VL2)
+    assert dp.angles.layout == (rt.ANGLES_ANTIPODAL_ADJACENT if order == ADJ else rt.ANGLES_ANTIPODAL)
     dp.run_gpu(1)
     so, To = dp.run_oracle(1, "plm_vl2")
     assert rel_err(dp.host(dp.I), so.I) < TOL[dtype]
