@@ -201,3 +201,50 @@ def test_plm_converges_faster_than_first_order():
     assert 0.6 < order1 < 1.3
     assert order2 > 1.3  # Barth-Jespersen clips at extrema on the jittered mesh: measured 1.47 (8->16), 1.61 (16->32)
     assert e2[1] < 0.4 * e1[1]
+
+
+@pytest.mark.parametrize("lam_dt", [0.2, 1.0, 20.0])
+@pytest.mark.parametrize("moving", [False, True])
+def test_vl2_predictor_applies_the_half_step_source(lam_dt, moving):
+    """The van Leer predictor (section 2 steps 2b and 4, section 2.2 item ii) includes the
+    source over dt/2 in the half-step state the stage-2 fluxes are built from.
+
+    In a uniform pure absorber (kappa_s = 0, kappa_P = kappa_J = kappa, gas at rest and so
+    heavy that B = a T^4/4 pi stays fixed) the implicit update of eq. 28 over a time tau is
+    the affine map I -> B + (I - B)/(1 + lam tau) with lam = cbar rho kappa, the same in every
+    cell.  Transport keeps a uniform field uniform (the volume update is the geometric
+    conservation law), the limited gradient is linear and the Barth-Jespersen factor is
+    invariant under shifts and positive scalings, so with v = I^n - B:
+      * the predictor's half-step state is B + (transported v)/(1 + lam dt/2),
+      * its stage-2 charge change is the source-free one times 1/(1 + lam dt/2),
+      * and the final source divides the deviation from B by (1 + lam dt).
+    Hence  (I^{n+1} - B)(1 + lam dt) - (V/V') v  =  [I_free - B - (V/V') v] / (1 + lam dt/2),
+    where I_free is the same step with no source at all.  Leaving the source out of the
+    predictor (factor 1) or taking it over dt (factor 1/(1 + lam dt)) breaks the identity."""
+    m = inp.voronoi_mesh(8, 0.2, seed=31)
+    d, w = inp.angle_set(24)
+    N, K = m.n_cells, d.shape[0]
+    rng = np.random.default_rng(32)
+    vel = rng.normal(0.0, 0.1, size=(N, 3)) if moving else np.zeros((N, 3))
+    om = orc.OracleMesh(m, vel)
+    phys = inp.Physics(c_red=100.0, c_light=100.0)
+    dt = 0.3 * np.min(m.vol) ** (1 / 3) / phys.c_red
+    rho_val = 1e20                      # the gas absorbs the radiation's momentum without moving
+    kap = lam_dt / (dt * phys.c_red * rho_val)
+    rho = np.full(N, rho_val)
+    kP = np.full(N, kap)
+    ks = np.zeros(N)
+    T0 = 1.0
+    B = phys.a_rad * T0 ** 4 / (4 * np.pi)
+    kv = 2 * np.pi * np.array([1.0, 2.0, -1.0])
+    I = B * (1.0 + 0.3 * np.sin(m.com @ kv)[:, None] + 0.1 * rng.normal(size=(N, K)))
+    st = orc.OState(I, m.vol.copy(), np.zeros((N, 3)), rho * phys.cv * T0)
+    full, T = orc.step(om, d, w, phys, dt, st, rho, kP, kP, ks, "plm_vl2")
+    free, _ = orc.step(om, d, w, phys, dt, st, rho, kP, kP, ks, "plm_vl2", with_source=False)
+    assert np.abs(T - T0).max() < 1e-15 and np.abs(full.mom).max() / rho_val < 1e-20
+    ratio = (m.vol / om.advance_volume(m.vol, dt))[:, None]
+    v = I - B
+    d_src = (full.I - B) * (1.0 + lam_dt) - ratio * v
+    d_free = free.I - B - ratio * v
+    assert np.abs(d_free).max() > 1e-2 * B                     # transport moves charge
+    np.testing.assert_allclose(d_src, d_free / (1.0 + 0.5 * lam_dt), rtol=0, atol=1e-13 * B * (1.0 + lam_dt))
