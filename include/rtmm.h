@@ -95,7 +95,7 @@ enum {
 /* Discrete ordinates: K unit directions and weights summing to one (device memory). */
 typedef struct {
   int32_t K;            /* 1 <= K <= k_max of the mesh (and <= RT_K_MAX) */
-  int32_t layout;       /* RT_ANGLES_*; set it with rt_angles_layout(); a wrong claim gives wrong results */
+  int32_t layout;       /* RT_ANGLES_*: an antipodal claim must first pass rt_angles_check() */
   const double *dir;    /* device [K][3], unit vectors */
   const double *weight; /* device [K], sum = 1 */
 } rt_angles;
@@ -118,6 +118,26 @@ int rt_version(void);
  * Errors: RT_EINVAL on NULL pointers or K outside [1, RT_K_MAX].
  */
 int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t *layout);
+
+/*
+ * Verify the layout an angle set claims, against its DEVICE arrays, and record the
+ * verified claim.  The paired kernels that serve the antipodal layouts take the
+ * antipode's direction as -n_k and its weight as W_k (section 2.3's quadrature of
+ * the moments and of the comoving weights W~ = N W / Gamma^2), so every call that
+ * receives an angle set claiming RT_ANGLES_ANTIPODAL or RT_ANGLES_ANTIPODAL_ADJACENT
+ * refuses it with RT_EINVAL unless this call recorded that exact claim (same K,
+ * layout, dir and weight pointers).  RT_ANGLES_GENERAL needs no check: the general
+ * kernels hold for any set.  The call copies dir [K][3] and weight [K] to the host
+ * (synchronising `stream`), classifies them as rt_angles_layout does, and returns
+ * RT_EINVAL (recording nothing) when the claim differs from what the arrays hold.
+ * The arrays must not change while the claim is recorded: call rt_angles_release
+ * before changing or freeing them.  Errors: RT_EINVAL (NULL, K outside
+ * [1, RT_K_MAX], unknown layout, false claim), RT_EHIP.
+ */
+int rt_angles_check(const rt_angles *angles, void *stream);
+
+/* Forget every recorded claim on the arrays of `angles` (no-op when there is none). */
+int rt_angles_release(const rt_angles *angles);
 
 /*
  * Upload a periodic Voronoi mesh and prepare it for steps (section 2: cells,
@@ -367,9 +387,14 @@ int rt_moments(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, 
                void *stream);
 
 /*
- * Conservation diagnostics into out[RT_NDIAG] (HOST): sum V E_g,
+ * Conservation diagnostics into out[RT_NDIAG] (HOST), the totals of section 2.3.1's
+ * energy and momentum balance in the reduced-speed-of-light approximation (eqs. 37-38,
+ * the radiation parts weighted by c/cbar and 1/(c cbar) as in eqs. 17-18): sum V E_g,
  * sum V (c/cbar) E_r, sum V rho v (3), sum V F_r/(c cbar) (3), min I, and the
- * number of non-finite entries of I, etot and mom.  Synchronises `stream`.
+ * number of non-finite entries of I, etot and mom.  The source update keeps
+ * E_g + (c/cbar) E_r and rho v + F_r/(c cbar) of every cell unchanged, and transport
+ * conserves sum V I of every angle, so the first two totals and the two momentum
+ * totals sum to constants on a periodic mesh.  Synchronises `stream`.
  * Returns RT_ENONFINITE (with out filled) when that count is non-zero.
  */
 int rt_diagnostics(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I,

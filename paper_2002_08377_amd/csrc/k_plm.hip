@@ -134,7 +134,7 @@ hipError_t launch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s
   const void *rel = std::is_same<T, double>::value ? (const void *)m->hf_rel64 : (const void *)m->hf_rel32;
   const int cap = cpb == 16 ? m->hf_cap16 : m->hf_cap32;
   const size_t smem = (3 * sizeof(V4) + sizeof(int32_t)) * (size_t)cap;
-  if (smem > 65536) return hipErrorInvalidConfiguration;
+  if (smem > (size_t)m->lds_max) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_gradient<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s, m->N,
                      K, m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, cap, nblk);
   return hipGetLastError();

@@ -210,8 +210,9 @@ k_step(rt_step_args a, int64_t nblk) {
 }
 
 // Staging needs (records per half-face) x (half-faces of the largest range of the
-// workgroup's cells) bytes of LDS; a layout that would need more than 64 KiB is
-// refused with hipErrorInvalidConfiguration (the dispatch then tries another).
+// workgroup's cells) bytes of LDS; a layout that would need more than a workgroup may
+// use (160 KiB on gfx950) is refused with hipErrorInvalidConfiguration (the dispatch then
+// tries the general layout, whose 16-cell workgroups the upload checked to fit).
 template <typename T, int LPC, int APL, bool FULL, int PAIRED>
 hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
   using V4 = typename rt_vec4<T>::type;
@@ -223,7 +224,7 @@ hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
   const dim3 grid((unsigned)rt_grid_for(nblk)), block(RT_BLOCK);
   const size_t per = (a.do_transport == 2 ? 3 : 1) * sizeof(V4) + sizeof(int32_t);
   const size_t smem = a.do_transport ? per * (size_t)a.hf_cap : 0;
-  if (smem > 65536) return hipErrorInvalidConfiguration;
+  if (smem > (size_t)a.lds_max) return hipErrorInvalidConfiguration;
   switch (a.do_transport) {
     case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
@@ -254,26 +255,37 @@ template <typename T, int PAIRED> hipError_t dispatch_paired(const rt_step_args 
   return hipErrorInvalidConfiguration;
 }
 
-template <typename T> hipError_t dispatch_general(const rt_step_args &a, hipStream_t s) {
-  switch (rt_step_lanes(a.K, 0)) {
-    case 0x1001: return launch<T, 16, 1>(a, s);
-    case 0x1002: return launch<T, 16, 2>(a, s);
-    case 0x1003: return launch<T, 16, 3>(a, s);
-    case 0x1004: return launch<T, 16, 4>(a, s);
-    case 0x1005: return launch<T, 16, 5>(a, s);
-    case 0x1006: return launch<T, 16, 6>(a, s);
-    case 0x1007: return launch<T, 16, 7>(a, s);
-    case 0x1008: return launch<T, 16, 8>(a, s);
-    case 0x0801: return launch<T, 8, 1>(a, s);
-    case 0x0802: return launch<T, 8, 2>(a, s);
-    case 0x0803: return launch<T, 8, 3>(a, s);
-    case 0x0804: return launch<T, 8, 4>(a, s);
-    case 0x0805: return launch<T, 8, 5>(a, s);
-    case 0x0806: return launch<T, 8, 6>(a, s);
-    case 0x0807: return launch<T, 8, 7>(a, s);
-    case 0x0808: return launch<T, 8, 8>(a, s);
+template <typename T> hipError_t dispatch_general16(const rt_step_args &a, hipStream_t s) {
+  switch ((a.K + 15) / 16) {
+    case 1: return launch<T, 16, 1>(a, s);
+    case 2: return launch<T, 16, 2>(a, s);
+    case 3: return launch<T, 16, 3>(a, s);
+    case 4: return launch<T, 16, 4>(a, s);
+    case 5: return launch<T, 16, 5>(a, s);
+    case 6: return launch<T, 16, 6>(a, s);
+    case 7: return launch<T, 16, 7>(a, s);
+    case 8: return launch<T, 16, 8>(a, s);
   }
   return hipErrorInvalidValue;
+}
+
+// The general layout for K; when 8 lanes per cell (32-cell workgroups) cannot stage their
+// face records, 16 lanes (16-cell workgroups, which the upload checked to fit) serve K.
+template <typename T> hipError_t dispatch_general(const rt_step_args &a, hipStream_t s) {
+  const int lanes = rt_step_lanes(a.K, 0);
+  if ((lanes >> 8) == 16) return dispatch_general16<T>(a, s);
+  hipError_t e = hipErrorInvalidValue;
+  switch (lanes) {
+    case 0x0801: e = launch<T, 8, 1>(a, s); break;
+    case 0x0802: e = launch<T, 8, 2>(a, s); break;
+    case 0x0803: e = launch<T, 8, 3>(a, s); break;
+    case 0x0804: e = launch<T, 8, 4>(a, s); break;
+    case 0x0805: e = launch<T, 8, 5>(a, s); break;
+    case 0x0806: e = launch<T, 8, 6>(a, s); break;
+    case 0x0807: e = launch<T, 8, 7>(a, s); break;
+    case 0x0808: e = launch<T, 8, 8>(a, s); break;
+  }
+  return e == hipErrorInvalidConfiguration ? dispatch_general16<T>(a, s) : e;
 }
 
 // Antipodal sets take the paired kernel when it has a lane layout for K and its staging

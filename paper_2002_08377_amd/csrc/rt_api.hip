@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -54,6 +55,24 @@ void free_mesh_arrays(rt_mesh *m) {
 
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
+// Antipodal layout claims verified by rt_angles_check against the device arrays they name.
+// A claim of RT_ANGLES_ANTIPODAL or RT_ANGLES_ANTIPODAL_ADJACENT reaches the paired
+// kernels (which take the antipode's direction as -n and its weight as the angle's)
+// only if it is recorded here.
+struct checked_claim {
+  const double *dir, *weight;
+  int32_t K, layout;
+};
+std::mutex g_claims_mu;
+std::vector<checked_claim> g_claims;
+
+bool claim_checked(const rt_angles *a) {
+  std::lock_guard<std::mutex> lk(g_claims_mu);
+  for (const checked_claim &c : g_claims)
+    if (c.dir == a->dir && c.weight == a->weight && c.K == a->K && c.layout == a->layout) return true;
+  return false;
+}
+
 int check_call(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
   if (!m) return fail(RT_EINVAL, "mesh is NULL");
   if (!p) return fail(RT_EINVAL, "params is NULL");
@@ -64,6 +83,8 @@ int check_call(const rt_mesh *m, const rt_params *p, const rt_angles *a) {
   if (a->layout != RT_ANGLES_GENERAL &&
       !((a->layout == RT_ANGLES_ANTIPODAL || a->layout == RT_ANGLES_ANTIPODAL_ADJACENT) && a->K % 2 == 0))
     return fail(RT_EINVAL, "invalid angle layout %d for K=%d", a->layout, a->K);
+  if (a->layout != RT_ANGLES_GENERAL && !claim_checked(a))
+    return fail(RT_EINVAL, "angle layout %d (K=%d) was not verified by rt_angles_check", a->layout, a->K);
   if (!(p->dt > 0.0) || !isfinite(p->dt)) return fail(RT_EINVAL, "dt must be positive and finite");
   if (!(p->c_red > 0.0) || !isfinite(p->c_red)) return fail(RT_EINVAL, "c_red must be positive");
   if (!(p->c_light >= p->c_red) || !isfinite(p->c_light)) return fail(RT_EINVAL, "c_light must be >= c_red");
@@ -111,6 +132,7 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
   s.m_gain = 4.0 * M_PI / p->c_red;
   s.a_4pi = p->a_rad / (4.0 * M_PI);
   s.paired = rt_pair_kind(a->layout);
+  s.lds_max = m->lds_max;
   s.hf_cap16 = m->hf_cap16;
   s.hf_cap32 = m->hf_cap32;
   s.hf_cap64 = m->hf_cap64;
@@ -218,6 +240,39 @@ int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t
   return RT_OK;
 }
 
+int rt_angles_check(const rt_angles *a, void *stream) {
+  if (!a) return fail(RT_EINVAL, "angles is NULL");
+  if (a->K < 1 || a->K > RT_K_MAX) return fail(RT_EINVAL, "K=%d outside [1, %d]", a->K, RT_K_MAX);
+  if (!a->dir || !a->weight) return fail(RT_EINVAL, "angle arrays are NULL");
+  if (a->layout != RT_ANGLES_GENERAL && a->layout != RT_ANGLES_ANTIPODAL && a->layout != RT_ANGLES_ANTIPODAL_ADJACENT)
+    return fail(RT_EINVAL, "unknown angle layout %d", a->layout);
+  if (a->layout == RT_ANGLES_GENERAL) return RT_OK;  // the general kernels hold for any set
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> d(3 * (size_t)a->K), w((size_t)a->K);
+  RT_HIP(hipMemcpyAsync(d.data(), a->dir, sizeof(double) * d.size(), hipMemcpyDeviceToHost, st), "copy directions");
+  RT_HIP(hipMemcpyAsync(w.data(), a->weight, sizeof(double) * w.size(), hipMemcpyDeviceToHost, st), "copy weights");
+  RT_HIP(hipStreamSynchronize(st), "angle copy");
+  int32_t found = RT_ANGLES_GENERAL;
+  int rc = rt_angles_layout(a->K, d.data(), w.data(), &found);
+  if (rc) return rc;
+  if (found != a->layout)
+    return fail(RT_EINVAL, "angle set claims layout %d but its arrays have layout %d", a->layout, found);
+  std::lock_guard<std::mutex> lk(g_claims_mu);
+  for (const checked_claim &c : g_claims)
+    if (c.dir == a->dir && c.weight == a->weight && c.K == a->K && c.layout == a->layout) return RT_OK;
+  g_claims.push_back(checked_claim{a->dir, a->weight, a->K, a->layout});
+  return RT_OK;
+}
+
+int rt_angles_release(const rt_angles *a) {
+  if (!a) return fail(RT_EINVAL, "angles is NULL");
+  std::lock_guard<std::mutex> lk(g_claims_mu);
+  g_claims.erase(std::remove_if(g_claims.begin(), g_claims.end(),
+                                [a](const checked_claim &c) { return c.dir == a->dir && c.weight == a->weight; }),
+                 g_claims.end());
+  return RT_OK;
+}
+
 int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t flags, const double *gen,
                    const double *com, const double *vol, const double *mesh_vel, const int32_t *face_cells,
                    const int8_t *face_shift, const double *face_area, const double *face_normal,
@@ -308,6 +363,25 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
     fill_order(64, order64);
   }
   (void)hipGetDevice(&m->device);
+  {
+    // Every cell-parallel kernel that reads face records stages a workgroup's records in
+    // LDS; the general layouts (16 cells per workgroup) must fit, the others fall back to them.
+    int lds = 0;
+    hipError_t ea = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+    if (ea != hipSuccess || lds <= 0) {
+      delete m;
+      return hip_fail(ea != hipSuccess ? ea : hipErrorInvalidValue, "LDS size query");
+    }
+    m->lds_max = lds;
+    // bytes per half-face: FP64 upwind 36, FP64 PLM stage 2 and gradient 100
+    const size_t per = (flags & RT_MESH_PLM) ? 3 * sizeof(double4) + sizeof(int32_t) : sizeof(double4) + sizeof(int32_t);
+    if (per * (size_t)m->hf_cap16 > (size_t)lds) {
+      const int cap = m->hf_cap16;
+      delete m;
+      return fail(RT_EINVAL, "16 consecutive cells have %d half-faces; their face records (%zu bytes) exceed the %d bytes of LDS a workgroup may use",
+                  cap, per * (size_t)cap, lds);
+    }
+  }
   m->N = N;
   m->F = F;
   m->H = H;

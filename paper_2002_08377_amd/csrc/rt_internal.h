@@ -35,6 +35,7 @@ struct rt_mesh {
   double *red;        // reduction partials, RT_NDIAG * n_red_blocks doubles
   double *red_mid;    // first fold of the partials, RT_NDIAG * RT_BLOCK doubles
   int64_t n_red_blocks;
+  int32_t lds_max;    // LDS bytes a workgroup may use on the upload's device
   int32_t hf_cap16;   // most half-faces of any 16 consecutive cells (workgroups of 16 cells)
   int32_t hf_cap32;   // same for 32 consecutive cells
   int32_t hf_cap64;   // same for 64 consecutive cells
@@ -80,6 +81,7 @@ struct rt_step_args {
   double a_4pi;       // a / 4 pi
   int paired;        // rt_pair_kind of the angle layout
   int hf_cap;        // LDS staging slots of the launched kernel (set at dispatch)
+  int lds_max;       // LDS bytes a workgroup may use
   int hf_cap16, hf_cap32, hf_cap64;  // half-faces of the largest range of 16 / 32 / 64 cells
   const uint8_t *wg_order16, *wg_order32, *wg_order64;  // cell order within workgroups
   const uint8_t *wg_order;                              // the one of the launched kernel

@@ -66,6 +66,8 @@ _SIGS = {
     "rt_diagnostics": [ctypes.c_void_p] * 9,
     "rt_moments": [ctypes.c_void_p] * 6,
     "rt_angles_layout": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "rt_angles_check": [ctypes.c_void_p, ctypes.c_void_p],
+    "rt_angles_release": [ctypes.c_void_p],
     "rt_marked_upload": [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 5
                         + [ctypes.c_double, ctypes.c_void_p],
     "rt_marked_free": [ctypes.c_void_p],
@@ -146,14 +148,33 @@ def angles_layout(dirs, weights) -> int:
 
 
 class AngleSet:
-    """Directions [K,3] and weights [K] resident on the device (float64), with their layout."""
+    """Directions [K,3] and weights [K] resident on the device (float64), with their layout.
 
-    def __init__(self, dirs, weights, device="cuda", layout=None):
+    The layout is detected from the host arrays unless given.  An antipodal layout is then
+    verified by the library against the device copies (rt_angles_check), which raises
+    RTError for a false claim; the claim is released when the set is freed."""
+
+    def __init__(self, dirs, weights, device="cuda", layout=None, stream=None):
         self.layout = angles_layout(dirs, weights) if layout is None else int(layout)
         self.dirs = torch.as_tensor(np.ascontiguousarray(dirs, dtype=np.float64), device=device)
         self.weights = torch.as_tensor(np.ascontiguousarray(weights, dtype=np.float64), device=device)
         self.K = int(self.dirs.shape[0])
         self.c = _Angles(self.K, self.layout, self.dirs.data_ptr(), self.weights.data_ptr())
+        self._checked = False
+        _check("rt_angles_check", lib().rt_angles_check(ctypes.byref(self.c), _stream(stream)))
+        self._checked = True
+
+    def free(self):
+        """Forget the library's record of this set's verified layout."""
+        if getattr(self, "_checked", False) and _lib is not None:
+            _lib.rt_angles_release(ctypes.byref(self.c))
+            self._checked = False
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Mesh:

@@ -60,3 +60,50 @@ class DeviceProblem:
 
     def host(self, t):
         return t.double().cpu().numpy()
+
+
+def elem_err(a, b, floor=0.0):
+    """Element-wise relative error max |a - b| / max(|b|, floor) (b nonzero where floor is 0)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor)))
+
+
+def vec_err(a, b, ref_scale):
+    """Per-cell relative error of 3-vectors: max_i |a_i - b_i| / ref_scale_i."""
+    a = np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    b = np.asarray(b, dtype=np.float64).reshape(-1, 3)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / ref_scale))
+
+
+# Regimes of the method's two speeds (section 2.1: c is the real speed of light in the
+# moments and the Lorentz factors, cbar the reduced one in transport) and of the face
+# motion (section 2.2 item iii: the upwind side follows cbar n.n_f - w~.n_f).
+#   "c":            cbar = c = 100, the common recipe (mesh velocity = gas velocity ~ 0.001 c);
+#   "reduced":      cbar = 10, c = 100, the same velocities;
+#   "reduced_fast": cbar = 10, c = 100, gas and mesh moving together at 0.3 cbar (v/c ~ 0.03,
+#                   up to ~0.05), so the face term decides the upwind side of every angle
+#                   within ~0.3 of grazing a face.
+REGIMES = {
+    "c": (100.0, 100.0, False),
+    "reduced": (10.0, 100.0, False),
+    "reduced_fast": (10.0, 100.0, True),
+}
+
+
+def regime_problem(regime, index=0, n=7, K=24, steps=3, seed=77):
+    """The seeded recipe of workload ``index`` at a reduced size, in one of REGIMES."""
+    c_red, c_light, fast = REGIMES[regime]
+    p = inp.make_problem(index, n=n, K=K, steps=steps)
+    p.phys = inp.Physics(c_red=c_red, c_light=c_light)
+    st = p.state
+    if fast:
+        rng = np.random.default_rng(seed)
+        N = p.mesh.n_cells
+        u0 = 0.3 * c_red * np.array([1.0, 2.0, 2.0]) / 3.0
+        w = u0 + rng.normal(0.0, 0.03 * c_red, size=(N, 3))
+        st.mesh_vel = np.ascontiguousarray(w)
+        st.mom = np.ascontiguousarray(st.rho[:, None] * w)
+        st.etot = st.rho * p.phys.cv * st.T + 0.5 * st.rho * np.sum(w * w, axis=1)
+    p.dt = inp.courant_dt(p.mesh, c_red)
+    return p

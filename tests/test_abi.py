@@ -150,3 +150,19 @@ def test_marked_upload_validates_on_the_host():
     assert rc == rt.RT_EINVAL and b"tau" in msg
     assert out.value is None
     assert L.rt_marked_free(None) == rt.RT_OK
+
+
+def test_angles_check_rejects_bad_claims_on_the_host():
+    """rt_angles_check refuses NULL sets, K out of range and unknown layouts before it
+    reads any device memory, and accepts a general claim without reading it."""
+    L = rt.lib()
+    assert L.rt_angles_check(None, None) == rt.RT_EINVAL
+    assert L.rt_angles_release(None) == rt.RT_EINVAL
+    bogus = 0x1000  # never dereferenced on these paths
+    for K, layout, d, w in ((0, 0, bogus, bogus), (rt.K_MAX + 1, 0, bogus, bogus), (8, 1, None, bogus),
+                            (8, 7, bogus, bogus)):
+        a = rt._Angles(K, layout, d, w)
+        assert L.rt_angles_check(ctypes.byref(a), None) == rt.RT_EINVAL, (K, layout)
+    a = rt._Angles(8, rt.ANGLES_GENERAL, bogus, bogus)
+    assert L.rt_angles_check(ctypes.byref(a), None) == rt.RT_OK
+    assert L.rt_angles_release(ctypes.byref(a)) == rt.RT_OK

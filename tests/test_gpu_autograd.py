@@ -25,7 +25,7 @@ import pytest
 import torch
 
 import oracle as orc
-from gpu_helpers import rel_err
+from gpu_helpers import elem_err, rel_err
 from paper_2002_08377_amd import inputs as inp
 from paper_2002_08377_amd import rt
 from paper_2002_08377_amd.autograd import RTSystem, flux_loss, rt_steps
@@ -202,8 +202,10 @@ def _loss_term_magnitude(p, u, IS):
         np.sum(np.abs(u[f]) * m.face_area[f] * np.sum(p.weights * np.abs(mu) * Iup, axis=1)))
 
 
+@pytest.mark.timeout(600)
 def test_adjoint_32c_48a_full_size_matches_finite_differences():
-    """Full size of the adjoint workload: 32^3 cells, 48 angles, 20 steps, FP64."""
+    """Full size of the adjoint workload: 32^3 cells, 48 angles, 20 steps, FP64: the whole
+    gradient against the oracle's, and 16 seeded cells against central differences."""
     p = inp.make_problem(2)
     system, x = _system(p)
     u = inp.loss_face_weights(p.mesh, p.seeds["omega"])
@@ -215,6 +217,18 @@ def test_adjoint_32c_48a_full_size_matches_finite_differences():
     floor = 64 * np.finfo(np.float64).eps * _loss_term_magnitude(p, u, IS.cpu().numpy())
     gk = gk.cpu().numpy()
     gI = gI.cpu().numpy()
+    # the whole gradient against the oracle's reverse mode (normwise, and element-wise over
+    # the entries above 1e-8 of the largest; the rest are the tails of the domain of dependence)
+    st = p.state
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    Lo, gIo, gko = orc.adjoint(om, p.dirs, p.weights, p.phys, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot),
+                               st.rho, st.kP, st.ks, p.steps, u)
+    err = {"L": abs(L - Lo) / abs(Lo), "gI": rel_err(gI, gIo), "gk": rel_err(gk, gko),
+           "gI_elem": elem_err(gI, gIo, 1e-8 * np.abs(gIo).max()), "gk_elem": elem_err(gk, gko, 1e-8 * np.abs(gko).max())}
+    print("adjoint 32^3 x 48 x 20 vs oracle:", {k: f"{v:.2e}" for k, v in err.items()})
+    assert err["L"] < 1e-12 and err["gI"] < 1e-10 and err["gk"] < 1e-10, err
+    assert err["gI_elem"] < 1e-8 and err["gk_elem"] < 1e-8, err
+    assert np.array_equal(gk == 0.0, gko == 0.0)
     k_star = p.seeds["fd_cells"].integers(0, p.dirs.shape[0], size=cells.size)
     assert np.count_nonzero(gk[cells]) > 0
     kap0 = x["kap"].cpu().numpy()
