@@ -281,6 +281,24 @@ int rt_flux_loss(rt_mesh *mesh, const rt_params *params, const rt_angles *angles
                  const double *face_weight, double *loss, void *seed, void *stream);
 
 /*
+ * rt_flux_loss for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels
+ * and results (bit for bit) as rt_flux_loss, but the per-workgroup partial sums live in a
+ * static device array of the library (2 MiB on every device it runs on, held until the
+ * process ends) instead of the mesh's scratch, and the call allocates nothing, on the
+ * device or the host.  Limit: one partial sum per workgroup of 16 cells (K a multiple of
+ * 16 or above 64) or 32 cells (other K), at most 261888 of them, i.e. meshes of up to
+ * 4,190,208 or 8,380,416 cells; larger meshes get RT_EINVAL.  Every partial the fold reads
+ * is written by the same call, so nothing needs clearing between calls.  All calls on one
+ * device share its array: calls that overlap in time on one device (other streams, other
+ * threads) race and must be serialised by the caller.  The mesh's device must be current
+ * (RT_EINVAL otherwise).  Errors as rt_flux_loss, plus RT_EHIP if the array's device
+ * address cannot be found.
+ */
+int rt_flux_loss_noalloc(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I,
+                         const double *face_weight, double *loss, void *seed, void *stream);
+
+/*
  * Multigroup implicit source update over params->dt (section 2.3, frequency
  * groups coupled only through the gas temperature), in place.  G groups
  * (1 <= G <= 16) of K angles each: I [G][N][K] (device, dtype, group-major),

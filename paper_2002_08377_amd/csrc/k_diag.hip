@@ -3,7 +3,14 @@
 // cell's lanes only.  Each cell group reduces over its angles, each workgroup
 // over its cells through LDS, then two folds over the per-workgroup partials in a
 // fixed order, so results are deterministic (no atomics).
+#include <mutex>
+
 #include "rt_device.h"
+
+// Scratch of the loss that allocates nothing: the per-workgroup partial sums in its first
+// RT_NOALLOC_PARTIALS doubles, the first fold in the last RT_BLOCK.  Each device holds
+// its own copy for the life of the process.
+static __device__ __align__(256) double rt_noalloc_scratch[RT_NOALLOC_PARTIALS + RT_BLOCK];
 
 namespace {
 
@@ -263,18 +270,21 @@ hipError_t launch_diag(const rt_mesh *m, int K, const double *dirs, const double
   return reduce_partials(m->red, nblk, ND, 1u << 8, m->red_mid, out, s);
 }
 
+// The loss into `partial` (one row per workgroup, at most `cap` rows), folded through `mid`
+// ([RT_BLOCK] rows) into *loss.
 template <typename T, int LPC, int APL>
 hipError_t launch_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
-                       const double *fw, double *loss, void *seed, hipStream_t s) {
+                       const double *fw, double *loss, void *seed, double *partial, double *mid, int64_t cap,
+                       hipStream_t s) {
   const int64_t cpb = RT_BLOCK / LPC;
   const int64_t nblk = (m->N + cpb - 1) / cpb;
-  if (nblk > m->n_red_blocks) return hipErrorInvalidValue;
+  if (nblk > cap) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_loss<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K,
-                     m->row_ptr, m->hf_face, m->hf_an64, dirs, W, c_light, (const T *)I, fw, (T *)seed, m->red,
+                     m->row_ptr, m->hf_face, m->hf_an64, dirs, W, c_light, (const T *)I, fw, (T *)seed, partial,
                      nblk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return reduce_partials(m->red, nblk, 1, 0u, m->red_mid, loss, s);
+  return reduce_partials(partial, nblk, 1, 0u, mid, loss, s);
 }
 
 #define RT_DISPATCH(FN, T, ...)                                   \
@@ -320,8 +330,28 @@ hipError_t moments_t(const rt_mesh *m, int K, const double *dirs, const double *
 
 template <typename T>
 hipError_t loss_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
-                  const double *fw, double *loss, void *seed, hipStream_t s) {
-  RT_DISPATCH(launch_loss, T, m, K, dirs, W, c_light, I, fw, loss, seed, s);
+                  const double *fw, double *loss, void *seed, double *partial, double *mid, int64_t cap,
+                  hipStream_t s) {
+  RT_DISPATCH(launch_loss, T, m, K, dirs, W, c_light, I, fw, loss, seed, partial, mid, cap, s);
+}
+
+// Device address of the scratch on each device, looked up once per device with that
+// device current (host code must never use the array's own name as a device pointer).
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[RT_MAX_DEVICES] = {};
+
+hipError_t noalloc_scratch(int device, double **out) {
+  if (device < 0 || device >= RT_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(rt_noalloc_scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = (double *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 }  // namespace
@@ -336,8 +366,28 @@ hipError_t rt_launch_diagnostics(const rt_mesh *m, int K, const double *dirs, co
 hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
                                const void *I, const double *face_weight, double *loss, void *seed, int dtype,
                                hipStream_t s) {
-  return dtype == RT_F32 ? loss_t<float>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s)
-                         : loss_t<double>(m, K, dirs, W, c_light, I, face_weight, loss, seed, s);
+  return dtype == RT_F32
+             ? loss_t<float>(m, K, dirs, W, c_light, I, face_weight, loss, seed, m->red, m->red_mid, m->n_red_blocks, s)
+             : loss_t<double>(m, K, dirs, W, c_light, I, face_weight, loss, seed, m->red, m->red_mid, m->n_red_blocks,
+                              s);
+}
+
+int64_t rt_loss_blocks(int64_t N, int K) {
+  const int64_t cpb = (K % 16 == 0 || K > 64) ? RT_BLOCK / 16 : RT_BLOCK / 8;  // the lane layout of RT_DISPATCH
+  return (N + cpb - 1) / cpb;
+}
+
+hipError_t rt_launch_flux_loss_noalloc(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                                       const void *I, const double *face_weight, double *loss, void *seed, int dtype,
+                                       hipStream_t s) {
+  double *scratch = nullptr;
+  const hipError_t e = noalloc_scratch(m->device, &scratch);
+  if (e != hipSuccess) return e;
+  double *mid = scratch + RT_NOALLOC_PARTIALS;
+  return dtype == RT_F32
+             ? loss_t<float>(m, K, dirs, W, c_light, I, face_weight, loss, seed, scratch, mid, RT_NOALLOC_PARTIALS, s)
+             : loss_t<double>(m, K, dirs, W, c_light, I, face_weight, loss, seed, scratch, mid, RT_NOALLOC_PARTIALS,
+                              s);
 }
 
 hipError_t rt_launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,

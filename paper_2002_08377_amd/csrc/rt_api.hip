@@ -636,6 +636,25 @@ int rt_flux_loss(rt_mesh *m, const rt_params *p, const rt_angles *a, const void 
   return RT_OK;
 }
 
+int rt_flux_loss_noalloc(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I,
+                         const double *face_weight, double *loss, void *seed, void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if ((rc = check_ptrs({I, face_weight, loss}))) return rc;
+  if (seed && !aligned8(seed)) return fail(RT_EINVAL, "seed is not 8-byte aligned");
+  int dev = -1;
+  RT_HIP(hipGetDevice(&dev), "current device");
+  if (dev != m->device) return fail(RT_EINVAL, "the mesh lives on device %d but device %d is current", m->device, dev);
+  const int64_t nblk = rt_loss_blocks(m->N, a->K);
+  if (nblk > RT_NOALLOC_PARTIALS)
+    return fail(RT_EINVAL, "%lld cells at K=%d need %lld partial sums; the static scratch holds %d",
+                (long long)m->N, a->K, (long long)nblk, RT_NOALLOC_PARTIALS);
+  hipError_t e = rt_launch_flux_loss_noalloc(m, a->K, a->dir, a->weight, p->c_light, I, face_weight, loss, seed,
+                                             p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "loss kernel launch (static scratch)");
+  return RT_OK;
+}
+
 int rt_source_implicit_mg(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t G, const double *group_weight,
                           void *I, const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
                           const double *ks, double *T_new, void *stream) {

@@ -225,6 +225,14 @@ hipError_t rt_launch_marked(const rt_marked_args &a, int dtype, hipStream_t s);
 hipError_t rt_launch_flux_loss(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
                                const void *I, const double *face_weight, double *loss, void *seed, int dtype,
                                hipStream_t s);
+// The loss that allocates nothing: the same kernels as rt_launch_flux_loss, with the
+// partial sums in a static device array of RT_NOALLOC_PARTIALS + RT_BLOCK doubles (2 MiB).
+#define RT_NOALLOC_PARTIALS ((1 << 18) - RT_BLOCK)
+#define RT_MAX_DEVICES 64
+int64_t rt_loss_blocks(int64_t N, int K);  // partial sums one loss launch writes
+hipError_t rt_launch_flux_loss_noalloc(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                                       const void *I, const double *face_weight, double *loss, void *seed, int dtype,
+                                       hipStream_t s);
 hipError_t rt_launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
                              const void *I, double *out, int dtype, hipStream_t s);
 hipError_t rt_launch_diagnostics(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red,

@@ -63,6 +63,7 @@ _SIGS = {
     "rt_gradient": [ctypes.c_void_p] * 6,
     "rt_step_adjoint": [ctypes.c_void_p] * 17,
     "rt_flux_loss": [ctypes.c_void_p] * 8,
+    "rt_flux_loss_noalloc": [ctypes.c_void_p] * 8,
     "rt_diagnostics": [ctypes.c_void_p] * 9,
     "rt_moments": [ctypes.c_void_p] * 6,
     "rt_angles_layout": [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -419,6 +420,18 @@ def flux_loss(mesh, params, angles, I, face_weight, loss, seed=None, stream=None
                             _dev(loss, torch.float64, (1,), "loss"), _dev(seed, td, (N, K), "seed", True),
                             _stream(stream))
     _check("rt_flux_loss", rc)
+
+
+def flux_loss_noalloc(mesh, params, angles, I, face_weight, loss, seed=None, stream=None):
+    """rt_flux_loss_noalloc: flux_loss with the partial sums in the library's static scratch."""
+    N, K = _shapes(mesh, angles)
+    td = torch_dtype(params.dtype)
+    rc = lib().rt_flux_loss_noalloc(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c),
+                                    _dev(I, td, (N, K), "I"),
+                                    _dev(face_weight, torch.float64, (mesh.n_faces,), "face_weight"),
+                                    _dev(loss, torch.float64, (1,), "loss"), _dev(seed, td, (N, K), "seed", True),
+                                    _stream(stream))
+    _check("rt_flux_loss_noalloc", rc)
 
 
 def moments(mesh, params, angles, I, out, stream=None):
