@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rt_internal.h"
+#include "rt_mesh_host.h"
 
 namespace {
 
@@ -287,81 +288,21 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
       !face_centroid)
     return fail(RT_EINVAL, "a mesh array is NULL");
   if (!(box > 0.0) || !isfinite(box)) return fail(RT_EINVAL, "box must be positive");
-  for (int64_t i = 0; i < N; ++i)
-    if (!(vol[i] > 0.0) || !isfinite(vol[i])) return fail(RT_EINVAL, "cell %lld has volume <= 0", (long long)i);
-  // faces: indices, areas, normals; closure of every cell
-  std::vector<double> clo(3 * (size_t)N, 0.0);
-  std::vector<int32_t> cnt((size_t)N + 1, 0);
-  for (int64_t f = 0; f < F; ++f) {
-    const int32_t i = face_cells[2 * f], j = face_cells[2 * f + 1];
-    if (i < 0 || j < 0 || i >= N || j >= N || i == j)
-      return fail(RT_EINVAL, "face %lld has invalid cells (%d, %d)", (long long)f, i, j);
-    const double A = face_area[f];
-    if (!(A > 0.0) || !isfinite(A)) return fail(RT_EINVAL, "face %lld has area <= 0", (long long)f);
-    const double *n = &face_normal[3 * f];
-    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-    if (!(fabs(nn - 1.0) < 1e-10)) return fail(RT_EINVAL, "face %lld normal is not unit", (long long)f);
-    for (int c = 0; c < 3; ++c) {
-      if (face_shift[3 * f + c] < -1 || face_shift[3 * f + c] > 1)
-        return fail(RT_EINVAL, "face %lld shift outside {-1,0,1}", (long long)f);
-      clo[3 * (size_t)i + c] += A * n[c];
-      clo[3 * (size_t)j + c] -= A * n[c];
-    }
-    cnt[(size_t)i + 1]++;
-    cnt[(size_t)j + 1]++;
-  }
-  for (int64_t i = 0; i < N; ++i) {
-    const double r = sqrt(clo[3 * i] * clo[3 * i] + clo[3 * i + 1] * clo[3 * i + 1] + clo[3 * i + 2] * clo[3 * i + 2]);
-    if (!(r <= 1e-8 * pow(vol[i], 2.0 / 3.0)))
-      return fail(RT_EINVAL, "cell %lld is not closed: |sum A n| = %g", (long long)i, r);
-  }
-  // half-face index grouped by cell, faces in input order within a cell
-  std::vector<int32_t> row_ptr((size_t)N + 1, 0);
-  for (int64_t i = 0; i < N; ++i) row_ptr[(size_t)i + 1] = row_ptr[(size_t)i] + cnt[(size_t)i + 1];
-  const int64_t H = 2 * F;
-  std::vector<int32_t> hf_face((size_t)H);
+  rt_host_mesh hm;
   {
-    std::vector<int32_t> fill(row_ptr.begin(), row_ptr.end() - 1);
-    for (int64_t f = 0; f < F; ++f) {
-      const int32_t i = face_cells[2 * f], j = face_cells[2 * f + 1];
-      hf_face[(size_t)fill[(size_t)i]++] = (int32_t)f;
-      hf_face[(size_t)fill[(size_t)j]++] = (int32_t)(-f - 1);
-    }
+    const std::string why = rt_build_host_mesh(N, F, vol, face_cells, face_shift, face_area, face_normal, hm);
+    if (!why.empty()) return fail(RT_EINVAL, "%s", why.c_str());
   }
+  const int64_t H = 2 * F;
+  const std::vector<int32_t> &row_ptr = hm.row_ptr;
+  const std::vector<int32_t> &hf_face = hm.hf_face;
 
   rt_mesh *m = new rt_mesh;
   memset(m, 0, sizeof *m);
-  for (int64_t c = 0; c < N; c += 16) {
-    const int64_t e = c + 16 < N ? c + 16 : N;
-    m->hf_cap16 = std::max<int32_t>(m->hf_cap16, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
-  }
-  for (int64_t c = 0; c < N; c += 32) {
-    const int64_t e = c + 32 < N ? c + 32 : N;
-    m->hf_cap32 = std::max<int32_t>(m->hf_cap32, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
-  }
-  for (int64_t c = 0; c < N; c += 64) {
-    const int64_t e = c + 64 < N ? c + 64 : N;
-    m->hf_cap64 = std::max<int32_t>(m->hf_cap64, row_ptr[(size_t)e] - row_ptr[(size_t)c]);
-  }
-  // within every workgroup of 16 / 32 / 64 consecutive cells, order the cells by face count
-  std::vector<uint8_t> order16((size_t)N), order32((size_t)N), order64((size_t)N);
-  {
-    std::vector<int> idx;
-    auto fill_order = [&](int cpb, std::vector<uint8_t> &ord) {
-      for (int64_t c = 0; c < N; c += cpb) {
-        const int n = (int)std::min<int64_t>(cpb, N - c);
-        idx.resize((size_t)n);
-        for (int g = 0; g < n; ++g) idx[(size_t)g] = g;
-        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
-          return cnt[(size_t)(c + x) + 1] < cnt[(size_t)(c + y) + 1];
-        });
-        for (int g = 0; g < n; ++g) ord[(size_t)(c + g)] = (uint8_t)idx[(size_t)g];
-      }
-    };
-    fill_order(16, order16);
-    fill_order(32, order32);
-    fill_order(64, order64);
-  }
+  m->hf_cap16 = hm.hf_cap16;
+  m->hf_cap32 = hm.hf_cap32;
+  m->hf_cap64 = hm.hf_cap64;
+  const std::vector<uint8_t> &order16 = hm.order16, &order32 = hm.order32, &order64 = hm.order64;
   (void)hipGetDevice(&m->device);
   {
     // Every cell-parallel kernel that reads face records stages a workgroup's records in

@@ -16,6 +16,8 @@
 
 #undef I
 
+#define DRV_PI 3.14159265358979323846
+
 typedef struct {
   int64_t n_cells, n_faces;
   const double *gen, *com, *vol, *mesh_vel;
@@ -157,7 +159,7 @@ int main(void) {
     etot[i] = rho[i] * cv * Tg + 0.5 * rho[i] * v2;
     kP[i] = kJ[i] = pow(10.0, 2.0 * uniform01() - 1.0);
     ks[i] = 0.1;
-    for (int k = 0; k < K; ++k) I0[i * K + k] = Tg * Tg * Tg * Tg / (4.0 * M_PI) * (0.9 + 0.2 * uniform01());
+    for (int k = 0; k < K; ++k) I0[i * K + k] = Tg * Tg * Tg * Tg / (4.0 * DRV_PI) * (0.9 + 0.2 * uniform01());
   }
 
   /* transport: charges V I of every angle are conserved */
@@ -183,7 +185,7 @@ int main(void) {
   for (int64_t i = 0; i < N; ++i) {
     double e = 0.0;
     for (int k = 0; k < K; ++k) e += W[k] * I1[i * K + k];
-    Eb[i] = etot[i] + 4.0 * M_PI * c_light / c_red * e;
+    Eb[i] = etot[i] + 4.0 * DRV_PI * c_light / c_red * e;
   }
   double *mom1 = xcalloc(3 * N, sizeof(double)), *etot1 = xcalloc(N, sizeof(double));
   memcpy(I2, I1, sizeof(double) * N * K);
@@ -193,7 +195,7 @@ int main(void) {
   for (int64_t i = 0; i < N; ++i) {
     double e = 0.0;
     for (int k = 0; k < K; ++k) e += W[k] * I2[i * K + k];
-    const double Ea = etot1[i] + 4.0 * M_PI * c_light / c_red * e;
+    const double Ea = etot1[i] + 4.0 * DRV_PI * c_light / c_red * e;
     CHECK(fabs(Ea - Eb[i]) <= 1e-13 * fabs(Eb[i]), "cell %lld energy %.17g -> %.17g", (long long)i, Eb[i], Ea);
     CHECK(T[i] > 0.0 && isfinite(T[i]), "cell %lld temperature %g", (long long)i, T[i]);
   }
