@@ -233,8 +233,8 @@ def _ms_per_call(fn, reps, warmup=2):
 
 
 def _roofline(ms, nbytes, ops=None):
-    """HBM roofline of `nbytes` algorithmic bytes (and the ALU one of `ops`, if given) in `ms`; the
-    bound whose peak needs more time comes first, the other beside it."""
+    """HBM roofline of `nbytes` algorithmic bytes in `ms`, with the ALU one of `ops` (if given)
+    beside it."""
     t = ms * 1e-3
     hbm = {"bound": "hbm", "achieved": round(nbytes / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(nbytes / t / 1e9 / HBM_PEAK_GBS, 4), "algorithmic_per_launch": int(nbytes)}
@@ -242,9 +242,8 @@ def _roofline(ms, nbytes, ops=None):
         return hbm
     alu = {"bound": "alu", "achieved": round(ops / t / 1e12, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "Top/s",
            "frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4), "algorithmic_per_launch": int(ops)}
-    main, other = (alu, hbm) if ops / ALU_PEAK_TOPS / 1e12 > nbytes / HBM_PEAK_GBS / 1e9 else (hbm, alu)
-    out = dict(main)
-    out["other"] = other
+    out = dict(hbm)
+    out["other"] = alu
     return out
 
 
@@ -372,15 +371,74 @@ def counters_summary(pmc_dir, copy_bytes):
     return {"source_hash": kernel_source_hash(), "scale": scale, "kernels": out}
 
 
+def copy_bandwidth(n, log, reps=20):
+    """Achievable HBM bandwidth of a plain streaming kernel on this GPU: torch's copy of n FP32
+    values (an intensity-sized array, read once and written once), timed with HIP events over
+    `reps` calls after two warm-up calls."""
+    import torch
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    ms = _ms_per_call(lambda: y.copy_(x), reps)
+    gbs = 2 * n * 4 / (ms * 1e-3) / 1e9
+    log(f"copy bandwidth: {gbs:.0f} GB/s ({ms:.4f} ms per copy of {n * 4} bytes)")
+    del x, y
+    return {"kernel": "torch copy_ of an FP32 array of the intensities' size", "bytes_per_launch": 2 * n * 4,
+            "ms": round(ms, 4), "achieved": round(gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, family / model / stepping, cache size."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if info:
+                        break  # the first processor's block is enough
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("vendor_id", "model name", "cpu family", "model", "stepping", "cache size", "cpu MHz"):
+                    info.setdefault(k, v)
     except OSError:
-        pass
-    return None
+        return None
+    if not info:
+        return None
+    return (f"{info.get('model name', '?')} (vendor {info.get('vendor_id', '?')}, family {info.get('cpu family', '?')}"
+            f", model {info.get('model', '?')}, stepping {info.get('stepping', '?')}, cache {info.get('cache size', '?')})")
+
+
+def cpu_config_timings(log):
+    """The oracle at the plain forward workload (12^3 cells x 24 angles x 10 first-order steps, all
+    of it) and at the PLM workload (64^3 cells x 80 angles, PLM-VL2: 3 of its 100 steps on all
+    threads, 1 on one thread), cell-angle updates per second."""
+    import oracle as orc
+    from paper_2002_08377_amd import inputs as inp
+    out = {}
+    threads = orc.num_threads()
+    for index, scheme, steps, one in ((0, "upwind1", 10, 10), (1, "plm_vl2", 3, 1)):
+        p = inp.make_problem(index)
+        st = p.state
+        N, K = st.I.shape
+        om = orc.OracleMesh(p.mesh, st.mesh_vel)
+        s0 = orc.OState(st.I, st.vol, st.mom, st.etot)
+        t0 = time.perf_counter()
+        orc.run(om, p.dirs, p.weights, p.phys, p.dt, s0, st.rho, st.kP, st.kJ, st.ks, steps, scheme)
+        dt = time.perf_counter() - t0
+        orc.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            orc.run(om, p.dirs, p.weights, p.phys, p.dt, s0, st.rho, st.kP, st.kJ, st.ks, one, scheme)
+            d1 = time.perf_counter() - t0
+        finally:
+            orc.set_num_threads(threads)
+        name = p.config.name
+        out[name] = {"value": N * K * steps / dt, "unit": "cell-angle updates/s", "cores": threads,
+                     "sample": f"{steps} of the {p.config.steps} {scheme} FP64 steps ({dt:.2f} s)",
+                     "one_thread": {"value": N * K * one / d1, "unit": "cell-angle updates/s", "cores": 1,
+                                    "sample": f"{one} step(s) ({d1:.2f} s)"}}
+        log(f"  oracle {name}: {steps} steps in {dt:.2f} s on {threads} threads, {one} in {d1:.2f} s on 1")
+    return out
 
 
 def cpu_baseline(prob, steps, log, one_thread_steps=1):
@@ -473,6 +531,7 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: 3 negated copies of {N * K * 4} bytes")
         del x, y
+    copy_bw = copy_bandwidth(N * K, log)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     # Angle order per form (the same directions; a storage choice of the caller): the FP32 form
     # runs fastest with the antipode of angle k at k + K/2 (each lane's 4-byte accesses of a
@@ -499,8 +558,9 @@ def main():
     err = float(np.max(np.abs(res["f32"]["I"] - res["f64"]["I"])) / np.max(np.abs(res["f64"]["I"])))
 
     def roof(name):
-        """The binding roofline of the fused step kernel: HBM or vector ALU, whichever needs more time
-        at its peak for the step's algorithmic bytes / operations; the other is reported beside it."""
+        """The HBM roofline of the fused step kernel (its algorithmic bytes over its mean launch
+        time), with the vector-ALU one of its algorithmic operations beside it, and both times at
+        peak."""
         t = res[name]["kernel_ms"] * 1e-3
         b = algorithmic_bytes(N, F, K, name)
         ops = algorithmic_ops(N, F, K)
@@ -509,13 +569,14 @@ def main():
         alu = {"bound": "alu", "achieved": round(ops / t / 1e12, 3), "peak": round(ALU_PEAK_TOPS, 2),
                "unit": "Top/s", "frac": round(ops / t / 1e12 / ALU_PEAK_TOPS, 4), "algorithmic_per_launch": int(ops)}
         t_hbm, t_alu = b / (HBM_PEAK_GBS * 1e9), ops / (ALU_PEAK_TOPS * 1e12)
-        main, other = (alu, hbm) if t_alu > t_hbm else (hbm, alu)
-        out = dict(main)
+        out = dict(hbm)
         out["traffic"] = measured_traffic(f"step_upwind1_{name}")
+        if copy_bw:
+            out["frac_of_copy"] = round(hbm["achieved"] / copy_bw["achieved"], 4)
         out["kernel"] = "k_step (fused upwind transport + implicit source)"
         out["kernel_ms"] = round(res[name]["kernel_ms"], 4)
         out["time_at_peak_ms"] = {"hbm": round(t_hbm * 1e3, 4), "alu": round(t_alu * 1e3, 4)}
-        out["other"] = other
+        out["other"] = alu
         return out
 
     out = {
@@ -540,6 +601,7 @@ def main():
         "roofline": roof("f32"),
         "fp64": {"value": ca / res["f64"]["wall"], "ms_per_step": res["f64"]["wall"] * 1e3 / args.steps,
                  "dtype": "f64", "roofline": roof("f64")},
+        "copy_bandwidth": copy_bw,
         "f32_over_f64": res["f64"]["wall"] / res["f32"]["wall"],
         "f32_vs_f64_rel_err_I": err,
     }
@@ -552,6 +614,7 @@ def main():
         out["plm"] = run_plm(log)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps, log)
+        out["cpu_baseline"]["configs"] = cpu_config_timings(log)
     print(json.dumps(out), flush=True)
 
 

@@ -78,7 +78,7 @@ class RTSteps(torch.autograd.Function):
         last = ((n_steps - 1) // ckpt_every) * ckpt_every if n_steps else 0  # first step of the last segment
         tape = []
         for n in range(n_steps):
-            if n % ckpt_every == 0:
+            if n % ckpt_every == 0 and n < last:  # the last segment is taped instead
                 ckpts.append((I.clone(), gas.clone()))
             if n >= last:
                 # the last segment: tape it now (the taped step gives the fused step's values)
@@ -119,9 +119,10 @@ class RTSteps(torch.autograd.Function):
         tape_I = [rec[0] for rec in ctx.last_tape]
         tape_I += [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps) - len(tape_I))]
         I2 = torch.empty((N, K), dtype=td, device=dev)
-        for seg in reversed(range(len(ctx.ckpts))):
-            if seg == len(ctx.ckpts) - 1:
-                tape = ctx.last_tape  # taped by the forward pass
+        n_seg = (ctx.n_steps + L - 1) // L
+        for seg in reversed(range(n_seg)):
+            if seg == n_seg - 1:
+                tape = ctx.last_tape  # taped by the forward pass (it has no checkpoint)
             else:
                 # each checkpoint is read once, so the recompute steps in its own buffers
                 I, gas = ctx.ckpts[seg]

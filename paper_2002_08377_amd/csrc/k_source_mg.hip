@@ -137,7 +137,11 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_mg(rt_mg_args a, int64_t nb
   const double Tnew = rt_quartic_root_from(Aq, rcv, Cq, Tn);
   const double T4 = Tnew * Tnew * Tnew * Tnew;
   const double planck = a.a_4pi * T4;
-  __builtin_amdgcn_wave_barrier();  // lane 0's LDS writes are read by the group's other lanes
+  // lane 0's LDS writes are read by the group's other lanes (same wave): release them to the
+  // wave, meet, then acquire
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   // pass 2: per group, update the row and book the energy and momentum handed over
   double dE = 0, dFx = 0, dFy = 0, dFz = 0;
