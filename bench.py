@@ -533,14 +533,14 @@ def main():
         del x, y
     copy_bw = copy_bandwidth(N * K, log)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    # Angle order per form (the same directions; a storage choice of the caller): the FP32 form
-    # runs fastest with the antipode of angle k at k + K/2 (each lane's 4-byte accesses of a
-    # cell cover 32 contiguous bytes), the FP64 form with antipodes side by side (one 16-byte
-    # access per pair).  The FP64 result is put back in the first order for the comparison.
+    # Angle order (the same directions; a storage choice of the caller): both forms run fastest
+    # with each antipode stored beside its angle (FP32: each lane moves two pairs with one
+    # 16-byte access; FP64: one pair per 16-byte access).  Results are put back in the
+    # first order for the comparison.
     perm = inp.adjacent_pair_order(K)
-    setup = {"f32": (prob, angles, None),
-             "f64": (inp.with_angle_order(prob, perm), rt.AngleSet(prob.dirs[perm], prob.weights[perm]),
-                     np.argsort(perm))}
+    inv = np.argsort(perm)
+    p_adj, a_adj = inp.with_angle_order(prob, perm), rt.AngleSet(prob.dirs[perm], prob.weights[perm])
+    setup = {"f32": (p_adj, a_adj, inv), "f64": (p_adj, a_adj, inv)}
     res = {}
     for name, code in (("f32", rt.F32), ("f64", rt.F64)):
         if name in forms:
@@ -595,8 +595,7 @@ def main():
         "config": {"workload": f"throughput_{round(N ** (1 / 3))}c_{K}a", "cells": N, "faces": F, "angles": K,
                    "steps": args.steps, "scheme": "upwind1",
                    "precision": "FP32 intensities and transport, FP64 source solve and bookkeeping",
-                   "angle_order": "level-symmetric S8 set; antipode of angle k at k + K/2 (FP32 form), "
-                                  "at k + 1 for even k (FP64 form)",
+                   "angle_order": "level-symmetric S8 set; antipode of angle k at k + 1 for even k",
                    "mesh": "periodic Voronoi of a +-0.2 jittered cubic lattice, Morton-ordered cells"},
         "roofline": roof("f32"),
         "fp64": {"value": ca / res["f64"]["wall"], "ms_per_step": res["f64"]["wall"] * 1e3 / args.steps,

@@ -246,6 +246,90 @@ __global__ __launch_bounds__(RT_BLOCK) void k_moments(int64_t N, int K, const do
   }
 }
 
+// Angle moments with 16-byte row chunks: 4 lanes per cell, lane l reading chunks
+// l, l + 4, ... (CPL of them) of its cell's row, so a wave's loads cover 16 rows 64 bytes
+// at a time (the cheapest access pattern for these rows).  Each angle's (W, n) comes from
+// LDS, where every lane at one position reads the same entry; the 4 lanes' moments are
+// summed by DPP quad permutations.  Needs rows of whole 16-byte chunks, 16-byte aligned.
+template <typename T, int CPL>
+__global__ __launch_bounds__(RT_BLOCK) void k_moments16(int64_t N, int K, const double *dirs, const double *W,
+                                                        double c_light, const T *I, double *out, int64_t nblk) {
+  constexpr int EPC = 16 / sizeof(T);  // elements per chunk
+  __shared__ double4 s_dw[RT_K_MAX];   // (W, n_x, n_y, n_z) per angle
+  for (int k = threadIdx.x; k < K; k += RT_BLOCK) s_dw[k] = double4{W[k], dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
+  __syncthreads();
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  const int64_t cell = lb * (RT_BLOCK / 4) + threadIdx.x / 4;
+  if (cell >= N) return;  // whole lane groups
+  const int l = threadIdx.x % 4;
+  const int nch = K / EPC;  // chunks per row
+  using V = typename rt_vec4<T>::type;
+  // the lane's chunks, all loads issued before any is used
+  const char *row = (const char *)(I + cell * (int64_t)K);
+  T x[CPL][EPC];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int ch = l + 4 * c;
+    if (ch < nch) {
+      if constexpr (EPC == 4) {
+        const float4 v = *(const float4 *)(row + 16 * ch);
+        x[c][0] = v.x; x[c][1] = v.y; x[c][2] = v.z; x[c][3] = v.w;
+      } else {
+        const double2 v = *(const double2 *)(row + 16 * ch);
+        x[c][0] = v.x; x[c][1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) x[c][e] = T(0);
+    }
+  }
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int ch = l + 4 * c;
+    if (ch >= nch) continue;
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+      const double4 d = s_dw[EPC * ch + e];
+      const double t = d.x * (double)x[c][e];
+      const double tx = t * d.y, ty = t * d.z, tz = t * d.w;
+      m[0] += t;
+      m[1] += tx;
+      m[2] += ty;
+      m[3] += tz;
+      m[4] += tx * d.y;
+      m[5] += ty * d.z;
+      m[6] += tz * d.w;
+      m[7] += tx * d.z;
+      m[8] += tx * d.w;
+      m[9] += ty * d.w;
+    }
+  }
+  const double fourpi = 4.0 * RT_PI;
+  double v[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) v[c] = rt_group_sum<4>(m[c]) * (c >= 1 && c <= 3 ? fourpi * c_light : fourpi);
+  // lane l writes components l, l + 4 and (l < 2) l + 8
+#pragma unroll
+  for (int b = 0; b < 10; b += 4) {
+    double o = v[b];
+#pragma unroll
+    for (int c = b + 1; c < b + 4 && c < 10; ++c)
+      if (l == c - b) o = v[c];
+    if (b + l < 10) out[10 * cell + b + l] = o;
+  }
+}
+
+template <typename T, int CPL>
+hipError_t launch_moments16(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                            const void *I, double *out, hipStream_t s) {
+  const int64_t nblk = (m->N + RT_BLOCK / 4 - 1) / (RT_BLOCK / 4);
+  hipLaunchKernelGGL((k_moments16<T, CPL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N, K, dirs,
+                     W, c_light, (const T *)I, out, nblk);
+  return hipGetLastError();
+}
+
 template <typename T, int LPC, int APL>
 hipError_t launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
                           double *out, hipStream_t s) {
@@ -325,6 +409,28 @@ hipError_t diag_t(const rt_mesh *m, int K, const double *dirs, const double *W, 
 template <typename T>
 hipError_t moments_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
                      double *out, hipStream_t s) {
+  // rows of whole 16-byte chunks starting 16-byte aligned: the chunked kernel, 4 lanes per cell
+  constexpr int EPC = 16 / sizeof(T);
+  if (K % EPC == 0 && ((uintptr_t)I & 15u) == 0) {
+    switch ((K / EPC + 3) / 4) {  // chunks per lane
+      case 1: return launch_moments16<T, 1>(m, K, dirs, W, c_light, I, out, s);
+      case 2: return launch_moments16<T, 2>(m, K, dirs, W, c_light, I, out, s);
+      case 3: return launch_moments16<T, 3>(m, K, dirs, W, c_light, I, out, s);
+      case 4: return launch_moments16<T, 4>(m, K, dirs, W, c_light, I, out, s);
+      case 5: return launch_moments16<T, 5>(m, K, dirs, W, c_light, I, out, s);
+      case 6: return launch_moments16<T, 6>(m, K, dirs, W, c_light, I, out, s);
+      case 7: return launch_moments16<T, 7>(m, K, dirs, W, c_light, I, out, s);
+      case 8: return launch_moments16<T, 8>(m, K, dirs, W, c_light, I, out, s);
+      case 9: return launch_moments16<T, 9>(m, K, dirs, W, c_light, I, out, s);
+      case 10: return launch_moments16<T, 10>(m, K, dirs, W, c_light, I, out, s);
+      case 11: return launch_moments16<T, 11>(m, K, dirs, W, c_light, I, out, s);
+      case 12: return launch_moments16<T, 12>(m, K, dirs, W, c_light, I, out, s);
+      case 13: return launch_moments16<T, 13>(m, K, dirs, W, c_light, I, out, s);
+      case 14: return launch_moments16<T, 14>(m, K, dirs, W, c_light, I, out, s);
+      case 15: return launch_moments16<T, 15>(m, K, dirs, W, c_light, I, out, s);
+      case 16: return launch_moments16<T, 16>(m, K, dirs, W, c_light, I, out, s);
+    }
+  }
   RT_DISPATCH(launch_moments, T, m, K, dirs, W, c_light, I, out, s);
 }
 

@@ -36,7 +36,11 @@ template <typename T, int LPC, int APL, int MODE, bool FULL, int PAIRED>
 __global__ __launch_bounds__(RT_BLOCK) __attribute__((amdgpu_waves_per_eu(rt_step_waves<T, MODE>::value))) void
 k_step(rt_step_args a, int64_t nblk) {
   using V4 = typename rt_vec4<T>::type;
-  using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED>;
+  // Runs of two pairs per lane (fewer, wider gathers): at 128^3 x 80 upwind, FP32 with
+  // antipodes side by side 1.30 -> 1.18 ms and FP64 with antipodes K/2 on 2.35 -> 2.04 ms
+  // (the other two forms within 3%).  PLM stage 2 addresses its four gathered rows per
+  // element and keeps one pair per slot (the runs made its FP64 form 1.59 -> 2.09 ms).
+  using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED, MODE != 2>;
   constexpr int P = Ang::P;
   constexpr int U = rt_batch<T, PAIRED>::U;
   constexpr int CPB = RT_BLOCK / LPC;
@@ -75,8 +79,11 @@ k_step(rt_step_args a, int64_t nblk) {
 
   const T *Iin = (const T *)a.I_in;
   const int64_t row = cell * (int64_t)K;
+  // the lane's base pointers into row 0 (its first angle, and its lone pair's angle)
+  const int k_single = Ang::SINGLE ? ang.k[P - 1] : ang.k[0];
+  const T *Iin_lane = Iin + ang.k[0], *Iin_single = Iin + k_single;
   T Ic[APL];
-  ang.read_row(Iin + row, Ic);
+  ang.read_lane(Iin_lane + row, Iin_single + row, Ic);
 
   double Vnew = 0.0;
   if (MODE != 0) {
@@ -90,37 +97,42 @@ k_step(rt_step_args a, int64_t nblk) {
     for (int q = 0; q < APL; ++q) acc[q] = MODE == 3 ? (T)Vn * Ic[q] : T(0);
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
+    // a neighbour's row is one multiply-add away from the lane's base pointers
+    const uint32_t row_bytes = (uint32_t)(K * sizeof(T));
     if (MODE == 1 || MODE == 3) {
       for (int h = h0; h < h1; h += U) {
         // batch metadata; slots past the cell's last face reuse face h0 with a zero record
-        int64_t j[U];
+        uint32_t j[U];
         V4 r[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const bool v = h + u < h1;
           const int i = (v ? h + u : h0) - H0;
-          j[u] = s_nbr[i];
+          j[u] = (uint32_t)s_nbr[i];
           r[u] = s_an[i];
           if (!v) r[u] = V4{T(0), T(0), T(0), T(0)};
         }
         T xn[U][APL];
 #pragma unroll
-        for (int u = 0; u < U; ++u) ang.read_row(Iin + j[u] * K, xn[u]);
+        for (int u = 0; u < U; ++u)
+          ang.read_lane(ang.lane_row(Iin_lane, j[u], row_bytes), ang.lane_row(Iin_single, j[u], row_bytes), xn[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          // g = dt (cbar (A n_out).n_k - A (w~.n)_out): charge leaving per unit upwind intensity
-          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, b = sd * r[u].w;
+          // g = dt (cbar (A n_out).n_k - A (w~.n)_out): charge leaving per unit upwind intensity,
+          // as three fused multiply-adds from -dt A (w~.n)_out.  Every operand of the face's
+          // other side is negated exactly, so both sides get bitwise opposite g (conservation).
+          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, nb = -(sd * r[u].w);
+          const T m2b = nb + nb;  // -2 dt A (w~.n)_out, exact
 #pragma unroll
           for (int q = 0; q < P; ++q) {
-            const T dot = ax * ang.x[q] + ay * ang.y[q] + az * ang.z[q];
-            const T g = dot - b;
+            const T g = fma(az, ang.z[q], fma(ay, ang.y[q], fma(ax, ang.x[q], nb)));
             if constexpr (MODE == 1) {
               acc[q] -= g * (g > T(0) ? Ic[q] : xn[u][q]);
             } else {
               acc[q] -= g > T(0) ? g * (Ic[q] - xn[u][q]) : T(0);
             }
             if (PAIRED) {
-              const T g2 = -dot - b;  // the antipodal angle
+              const T g2 = m2b - g;  // the antipodal angle: -(dot) - b
               if constexpr (MODE == 1) {
                 acc[q + P] -= g2 * (g2 > T(0) ? Ic[q + P] : xn[u][q + P]);
               } else {
@@ -145,13 +157,13 @@ k_step(rt_step_args a, int64_t nblk) {
       }
       constexpr int UP = sizeof(T) == 4 ? 2 : 1;
       for (int h = h0; h < h1; h += UP) {
-        int64_t j[UP];
+        uint32_t j[UP];
         V4 r[UP], r0[UP], r1[UP];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           const bool v = h + u < h1;
           const int i = (v ? h + u : h0) - H0;
-          j[u] = s_nbr[i];
+          j[u] = (uint32_t)s_nbr[i];
           r[u] = s_an[i];
           r0[u] = s_rel[2 * i];
           r1[u] = s_rel[2 * i + 1];
@@ -160,8 +172,8 @@ k_step(rt_step_args a, int64_t nblk) {
         T xh[UP][APL], xg0[UP][APL], xg1[UP][APL], xg2[UP][APL];
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-          const T *Hj = Ih + j[u] * K;
-          const T *Gj = G + j[u] * 3 * K;
+          const T *Hj = Ih + (uint64_t)j[u] * K;
+          const T *Gj = G + (uint64_t)j[u] * 3 * K;
 #pragma unroll
           for (int q = 0; q < APL; ++q) {
             const int k = ang.k[q];
@@ -173,10 +185,10 @@ k_step(rt_step_args a, int64_t nblk) {
         }
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
-          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, b = sd * r[u].w;
+          const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, nb = -(sd * r[u].w);
 #pragma unroll
           for (int q = 0; q < APL; ++q) {
-            const T g = ax * ang.dx(q) + ay * ang.dy(q) + az * ang.dz(q) - b;
+            const T g = fma(az, ang.dz(q), fma(ay, ang.dy(q), fma(ax, ang.dx(q), nb)));
             const T fs = hs[q] + gsx[q] * r0[u].x + gsy[q] * r0[u].y + gsz[q] * r0[u].z;
             const T fn = xh[u][q] + xg0[u][q] * r0[u].w + xg1[u][q] * r1[u].x + xg2[u][q] * r1[u].y;
             acc[q] -= g * (g > T(0) ? fs : fn);
@@ -197,7 +209,10 @@ k_step(rt_step_args a, int64_t nblk) {
       for (int q = 0; q < APL; ++q) Ic[q] = Ic[q] * cr + acc[q] * ci;
     }
     if constexpr (MODE == 1) {
-      if (a.I_star_out) ang.write_row((T *)a.I_star_out + row, Ic);
+      if (a.I_star_out) {
+        T *o = (T *)a.I_star_out + row;
+        ang.write_lane(o + ang.k[0], o + k_single, Ic);
+      }
     }
   }
 
@@ -205,7 +220,10 @@ k_step(rt_step_args a, int64_t nblk) {
     if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
   }
 
-  ang.write_row((T *)a.I_out + row, Ic);
+  {
+    T *o = (T *)a.I_out + row;
+    ang.write_lane(o + ang.k[0], o + k_single, Ic);
+  }
   if ((MODE == 1 || MODE == 2) && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
 }
 

@@ -9,13 +9,22 @@
 //    aliases angle 0 with weight 0 and is never stored.
 //  Paired layouts (needs K = LPC APL): the lane holds P = APL/2 angles and their
 //    antipodes (same weight) in slots q + P, so one stored direction serves both and
-//    one dot product per face serves both fluxes.
-//    PAIRED 1, antipode of angle k at k + K/2: angles k_q = l + LPC q and k_q + K/2.
-//    PAIRED 2, antipode of angle 2p at 2p + 1: pairs p_q = l + LPC q, angles 2 p_q and
-//      2 p_q + 1, adjacent in a row, so one 2-element load or store moves both and the
-//      LPC lanes of a cell cover 2 LPC consecutive elements per access.
-template <typename T, int LPC, int APL, bool FULL, int PAIRED> struct rt_step_angles {
+//    one dot product per face serves both fluxes.  Pair p is angles p and p + K/2 when
+//    PAIRED = 1 (antipode K/2 on) and angles 2p and 2p + 1 when PAIRED = 2 (antipode
+//    beside its angle, so a pair's two elements move with one wider access).
+//    TWOS false: slot q holds pair l + LPC q.
+//    TWOS true: pairs are dealt to the lanes two at a time: slot q < P2 = 2 floor(P/2)
+//      holds pair 2 (l + LPC floor(q/2)) + q mod 2, and when P is odd the last slot holds
+//      pair 2 LPC floor(P/2) + l.  A lane's pairs then come in runs of two consecutive
+//      pairs, which read_lane / write_lane move together (with PAIRED = 2, four
+//      consecutive elements: one 16-byte access in FP32).
+//  Both orders deal the same pairs to the same slots, so a step gives the same bits in
+//  either order.
+template <typename T, int LPC, int APL, bool FULL, int PAIRED, bool TWOS = false> struct rt_step_angles {
   static constexpr int P = PAIRED ? APL / 2 : APL;
+  static constexpr bool RUNS = TWOS && PAIRED;
+  static constexpr int P2 = RUNS ? 2 * (P / 2) : 0;     // slots holding runs of two pairs
+  static constexpr bool SINGLE = RUNS && P % 2 == 1;    // the last pair slot is a lone pair
   static constexpr bool PAIRED_LAYOUT = PAIRED != 0;
   static constexpr bool ADJACENT = PAIRED == 2;
   T x[P], y[P], z[P];
@@ -25,7 +34,9 @@ template <typename T, int LPC, int APL, bool FULL, int PAIRED> struct rt_step_an
   __device__ __forceinline__ void load(const double *dirs, const double *W, int K, int l) {
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const int kk = PAIRED == 2 ? 2 * (l + LPC * q) : l + LPC * q;
+      const int pr = !RUNS ? l + LPC * q
+                     : q < P2 ? 2 * (l + LPC * (q / 2)) + q % 2 : 2 * LPC * (P / 2) + l;  // pair of slot q
+      const int kk = PAIRED == 2 ? 2 * pr : pr;
       ok[q] = FULL || PAIRED || kk < K;
       k[q] = ok[q] ? kk : 0;
       x[q] = (T)dirs[3 * k[q]];
@@ -49,6 +60,48 @@ template <typename T, int LPC, int APL, bool FULL, int PAIRED> struct rt_step_an
   __device__ __forceinline__ void read_row(const T *p, T (&v)[APL]) const {
 #pragma unroll
     for (int q = 0; q < APL; ++q) v[q] = p[k[q]];
+  }
+  // Whether slot q holds the lone pair (its angle or its antipode).
+  static constexpr bool is_single(int q) { return SINGLE && (q == P - 1 || q == 2 * P - 1); }
+  // Offset of slot q from the lane's first angle k[0] (from k[P - 1] for the lone pair's
+  // slots); the same for every lane of a full layout (K = LPC APL), where the antipodes
+  // of PAIRED 1 sit K/2 = LPC P further on.
+  static constexpr int slot_offset(int q) {
+    const int qq = q < P ? q : q - P;
+    if (PAIRED == 1 && RUNS) return (is_single(q) ? 0 : 2 * LPC * (qq / 2) + qq % 2) + (q < P ? 0 : LPC * P);
+    if (PAIRED == 2 && RUNS) return (is_single(q) ? 0 : 4 * LPC * (qq / 2) + 2 * (qq % 2)) + (q < P ? 0 : 1);
+    if (PAIRED == 1) return LPC * qq + (q < P ? 0 : LPC * P);
+    if (PAIRED == 2) return 2 * LPC * qq + (q < P ? 0 : 1);
+    return LPC * q;
+  }
+  // The lane's elements of the row `r` of an [N][K] array: the lane's base pointers (row 0
+  // plus k[0], and plus k[P - 1] for a lone pair) move by a row stride (one 32 x 32 -> 64-bit
+  // multiply-add per row), and in a full layout every element sits at a compile-time offset
+  // from one of them.
+  __device__ __forceinline__ const T *lane_row(const T *lane_base, uint32_t r, uint32_t row_bytes) const {
+    return (const T *)((const char *)lane_base + (uint64_t)r * row_bytes);
+  }
+  __device__ __forceinline__ void read_lane(const T *pl, const T *ps, T (&v)[APL]) const {
+    if constexpr (FULL) {
+#pragma unroll
+      for (int q = 0; q < APL; ++q) v[q] = is_single(q) ? ps[slot_offset(q)] : pl[slot_offset(q)];
+    } else {
+#pragma unroll
+      for (int q = 0; q < APL; ++q) v[q] = pl[k[q] - k[0]];
+    }
+  }
+  __device__ __forceinline__ void write_lane(T *pl, T *ps, const T (&v)[APL]) const {
+    if constexpr (FULL) {
+#pragma unroll
+      for (int q = 0; q < APL; ++q) {
+        if (is_single(q)) ps[slot_offset(q)] = v[q];
+        else pl[slot_offset(q)] = v[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < APL; ++q)
+        if (ok[q]) pl[k[q] - k[0]] = v[q];
+    }
   }
   __device__ __forceinline__ void write_row(T *p, const T (&v)[APL]) const {
 #pragma unroll
