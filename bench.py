@@ -126,15 +126,20 @@ def run_form(prob, mesh, angles, dtype_code, steps, warmup, log):
 def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
     """Forward + adjoint throughput on the checkpointed workload (96^3 cells, 80 angles, 40 steps,
     FP32 transport, checkpoints every 8 steps): cell-angle updates per second of the forward steps,
-    the time covering the forward pass, the recompute and the adjoint of all steps."""
+    the time covering the forward pass, the recompute and the adjoint of all steps.  Beside it the
+    same pass with every step taped during the forward pass (no checkpoints, no recompute), which
+    holds all 40 steps' records at once."""
     import torch
     from paper_2002_08377_amd import autograd as ag
     from paper_2002_08377_amd import inputs as inp
     from paper_2002_08377_amd import rt
     t0 = time.perf_counter()
-    p = inp.make_problem(4)
+    p0 = inp.make_problem(4)
+    N, K = p0.state.I.shape
+    # antipodes stored beside their angles, as in the step measurement (the loss and the
+    # gradients do not depend on the storage order)
+    p = inp.with_angle_order(p0, inp.adjacent_pair_order(K))
     st, ph = p.state, p.phys
-    N, K = st.I.shape
     log(f"fwd+adj workload: {N} cells x {K} angles x {p.steps} steps; inputs built in "
         f"{time.perf_counter() - t0:.1f} s")
     mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_ADJOINT)
@@ -144,26 +149,34 @@ def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
     fw = d(inp.loss_face_weights(p.mesh, p.seeds["omega"]))
     I0, kap, etot, mom = d(st.I).float(), d(st.kP), d(st.etot), d(st.mom)
 
-    def once():
+    def once(every):
         x = [t.clone().requires_grad_() for t in (I0, kap, etot, mom)]
-        IS = ag.rt_steps(*x, system, p.steps, ckpt)[0]
+        IS = ag.rt_steps(*x, system, p.steps, every)[0]
         ag.flux_loss(IS, fw, system).backward()
         return x[1].grad
 
-    for _ in range(warmup):
-        once()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g = once()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
-    ok = bool(torch.isfinite(g).all())
+    def timed(every):
+        for _ in range(warmup):
+            once(every)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g = once(every)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, bool(torch.isfinite(g).all()), torch.cuda.max_memory_allocated()
+
+    dt, ok, mem = timed(ckpt)
+    dt_all, ok_all, mem_all = timed(p.steps)
     mesh.free()
-    log(f"  fwd+adj: {dt * 1e3:.1f} ms per pass of {p.steps} steps")
+    log(f"  fwd+adj: {dt * 1e3:.1f} ms per pass of {p.steps} steps (checkpoints every {ckpt}); "
+        f"{dt_all * 1e3:.1f} ms with every step taped")
     return {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s", "ms_per_pass": dt * 1e3,
             "workload": f"adjoint_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p.steps,
-            "checkpoint_every": ckpt, "dtype": "f32", "gradient_finite": ok}
+            "checkpoint_every": ckpt, "dtype": "f32", "angle_order": "antipodes adjacent",
+            "gradient_finite": ok, "peak_device_GB": round(mem / 1e9, 2),
+            "tape_every_step": {"value": N * K * p.steps / dt_all, "ms_per_pass": dt_all * 1e3,
+                                "gradient_finite": ok_all, "peak_device_GB": round(mem_all / 1e9, 2)}}
 
 
 def run_plm(log):

@@ -6,11 +6,12 @@ sections 2.2-2.3) with the fused step call and keeps a checkpoint of the state
 backward pass walks the segments in reverse: it restores the segment's
 checkpoint, re-runs its steps with the taped step call (the same fused kernel,
 so the same values bit for bit, which also stores the transported intensities
-I*), records the start-of-step volume and gas state, and then applies the
-per-step adjoint in reverse order.  The last segment is taped during the forward
-pass already (the backward starts there), so it is not run again.  Peak memory is
-therefore one checkpoint per segment plus `ckpt_every` recorded steps, instead of
-all S steps.
+I* and the per-cell sums and temperature of the source solve), records the
+start-of-step volume and gas state, and then reverses the segment's steps with
+one run-adjoint call (the transpose of each step fused with the source reverse of
+the step before it).  The last segment is taped during the forward pass already
+(the backward starts there), so it is not run again.  Peak memory is therefore one
+checkpoint per segment plus `ckpt_every` recorded steps, instead of all S steps.
 
 The opacities are tied, kappa_P = kappa_J = kappa_a, so dL/dkappa_a is the sum
 of the two partial derivatives; the library increments both into one buffer.
@@ -52,6 +53,17 @@ def _gas_views(gas):
     return gas[:N], gas[N:4 * N].view(N, 3), gas[4 * N:]
 
 
+def _record(N, dev):
+    """One step's record: the start-of-step gas state (as _gas_views) followed by the
+    step's source tape [N, SRC_TAPE], in one FP64 buffer."""
+    return torch.empty((5 + rt.SRC_TAPE) * N, dtype=torch.float64, device=dev)
+
+
+def _record_views(rec):
+    N = rec.shape[0] // (5 + rt.SRC_TAPE)
+    return rec[:5 * N], rec[5 * N:].view(N, rt.SRC_TAPE)
+
+
 class RTSteps(torch.autograd.Function):
     """(I^0, kappa_a, E_g^0, (rho v)^0) -> (I^S, E_g^S, (rho v)^S) after n_steps steps.
 
@@ -82,9 +94,11 @@ class RTSteps(torch.autograd.Function):
                 ckpts.append((I.clone(), gas.clone()))
             if n >= last:
                 # the last segment: tape it now (the taped step gives the fused step's values)
-                rec = (torch.empty_like(I), gas.clone())
+                rec = (torch.empty_like(I), _record(I.shape[0], I.device))
+                g_n, src = _record_views(rec[1])
+                g_n.copy_(gas)
                 rt.step_taped(system.mesh, system.params, system.angles, I, I2, rec[0], vol, system.rho, mom, etot,
-                              kap, kap, system.ks)
+                              kap, kap, system.ks, src_tape=src)
                 tape.append(rec)
             else:
                 rt.step(system.mesh, system.params, system.angles, I, I2, vol, system.rho, mom, etot, kap, kap,
@@ -118,6 +132,8 @@ class RTSteps(torch.autograd.Function):
         # segment's adjoint steps (enqueued first, on the same stream) have read them
         tape_I = [rec[0] for rec in ctx.last_tape]
         tape_I += [torch.empty((N, K), dtype=td, device=dev) for _ in range(min(L, ctx.n_steps) - len(tape_I))]
+        tape_R = [rec[1] for rec in ctx.last_tape]
+        tape_R += [_record(N, dev) for _ in range(min(L, ctx.n_steps) - len(tape_R))]
         I2 = torch.empty((N, K), dtype=td, device=dev)
         n_seg = (ctx.n_steps + L - 1) // L
         for seg in reversed(range(n_seg)):
@@ -131,14 +147,15 @@ class RTSteps(torch.autograd.Function):
                 nseg = min(L, ctx.n_steps - n0)
                 tape = []
                 for n in range(nseg):
-                    gas_n = gas.clone()
+                    g_n, src = _record_views(tape_R[n])
+                    g_n.copy_(gas)
                     rt.step_taped(s.mesh, s.params, s.angles, I, I2, tape_I[n], vol, s.rho, mom, etot, kap, kap,
-                                  s.ks)
+                                  s.ks, src_tape=src)
                     I, I2 = I2, I
-                    tape.append((tape_I[n], gas_n))
-            for I_star, gas_n in reversed(tape):
-                vol_n, mom_n, etot_n = _gas_views(gas_n)
-                rt.step_adjoint(s.mesh, s.params, s.angles, I_star, vol_n, s.rho, mom_n, etot_n, kap, kap, s.ks,
+                    tape.append((tape_I[n], tape_R[n]))
+            views = [(_gas_views(_record_views(r)[0]), _record_views(r)[1]) for _, r in tape]
+            rt.step_adjoint_run(s.mesh, s.params, s.angles, [i for i, _ in tape], [v[1] for v in views],
+                                [v[0][0] for v in views], [v[0][1] for v in views], s.rho, kap, kap, s.ks,
                                 lamI, lamE, lamM, dk, dk)
         ctx.ckpts = None
         ctx.last_tape = None

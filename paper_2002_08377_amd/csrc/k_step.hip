@@ -3,6 +3,7 @@
 // angles.  One pass reads the cell's intensity row, gathers the neighbour rows of
 // its faces through the half-face index (no atomics), updates the charges, runs the
 // source on the transported row while it is in registers, and writes the row once.
+#include "rt_source_vjp.h"
 #include "rt_step_common.h"
 
 namespace {
@@ -18,9 +19,13 @@ template <typename T, int PAIRED> struct rt_batch {
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
 // transport of PLM stage 2 (+ source); 3: the transpose of upwind transport (the
-// adjoint: input lam*/V' per cell and angle, output lam_i = V_i mu_i - sum over the
-// faces the cell is upwind of, g > 0, of g (mu_i - mu_j)).  Separate instantiations
-// keep each one's registers to what its own loop needs.
+// adjoint: input mu = lam*/V' per cell and angle, output lam_i = V_i mu_i - sum over the
+// faces the cell is upwind of, g > 0, of g (mu_i - mu_j)); 4: the transpose of step
+// n + 1 followed, in registers, by the reverse of the source of step n (output lam*/V'
+// of step n, so consecutive launches chain the reverse of a run of steps without
+// storing dL/dI in between); 5: the reverse of the source of step n alone (input dL/dI
+// of its output, read from the cell's own row only).  Separate instantiations keep each
+// one's registers to what its own code needs.
 //
 // The cells of a workgroup are consecutive, so their half-faces form one contiguous
 // range; it is staged in LDS (dynamic size: the largest range of any workgroup,
@@ -41,6 +46,8 @@ k_step(rt_step_args a, int64_t nblk) {
   // (the other two forms within 3%).  PLM stage 2 addresses its four gathered rows per
   // element and keeps one pair per slot (the runs made its FP64 form 1.59 -> 2.09 ms).
   using Ang = rt_step_angles<T, LPC, APL, FULL, PAIRED, MODE != 2>;
+  constexpr bool FACES = MODE >= 1 && MODE <= 4;  // the modes that read face records
+  constexpr bool TRANSPOSE = MODE == 3 || MODE == 4;
   constexpr int P = Ang::P;
   constexpr int U = rt_batch<T, PAIRED>::U;
   constexpr int CPB = RT_BLOCK / LPC;
@@ -57,7 +64,7 @@ k_step(rt_step_args a, int64_t nblk) {
   const int l = threadIdx.x % LPC;
   const int K = a.K;
   int H0 = 0;
-  if (MODE != 0) {
+  if (FACES) {
     const V4 *an = (const V4 *)a.hf_an;
     const V4 *rel = (const V4 *)a.hf_rel;
     const int64_t c1 = c0 + CPB < a.N ? c0 + CPB : a.N;
@@ -86,20 +93,22 @@ k_step(rt_step_args a, int64_t nblk) {
   ang.read_lane(Iin_lane + row, Iin_single + row, Ic);
 
   double Vnew = 0.0;
-  if (MODE != 0) {
+  if (MODE == 5) Vnew = a.vol_in[cell] + a.dt * a.D[cell];
+  if (FACES) {
     // ---- transport: charges V I minus the upwind charge through every face -------------
     const double Vn = a.vol_in[cell];
     const double dV = a.dt * a.D[cell];
-    Vnew = Vn + dV;
-    // the charge through the faces is accumulated apart from V I (the transpose adds V mu)
+    Vnew = Vn + dV;  // the end-of-step volume, formed as the forward step forms it
+    // the charge through the faces is accumulated apart from V I (the transpose adds V mu,
+    // with V the start-of-step volume of the step it transposes: step n + 1 in mode 4)
     T acc[APL];
 #pragma unroll
-    for (int q = 0; q < APL; ++q) acc[q] = MODE == 3 ? (T)Vn * Ic[q] : T(0);
+    for (int q = 0; q < APL; ++q) acc[q] = TRANSPOSE ? (T)(MODE == 4 ? Vnew : Vn) * Ic[q] : T(0);
     const T sc = (T)(a.dt * a.c_red), sd = (T)a.dt;
     const int h0 = a.row_ptr[cell], h1 = a.row_ptr[cell + 1];
     // a neighbour's row is one multiply-add away from the lane's base pointers
     const uint32_t row_bytes = (uint32_t)(K * sizeof(T));
-    if (MODE == 1 || MODE == 3) {
+    if (MODE == 1 || TRANSPOSE) {
       for (int h = h0; h < h1; h += U) {
         // batch metadata; slots past the cell's last face reuse face h0 with a zero record
         uint32_t j[U];
@@ -196,7 +205,7 @@ k_step(rt_step_args a, int64_t nblk) {
         }
       }
     }
-    if constexpr (MODE == 3) {
+    if constexpr (TRANSPOSE) {
 #pragma unroll
       for (int q = 0; q < APL; ++q) Ic[q] = acc[q];
     } else {
@@ -216,8 +225,16 @@ k_step(rt_step_args a, int64_t nblk) {
     }
   }
 
-  if constexpr (MODE != 3) {
+  if constexpr (MODE <= 2) {
     if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
+  }
+  if constexpr (MODE >= 4) {
+    // Ic holds dL/dI^{n+1} of the cell; the reverse of the source of step n turns it into
+    // dL/dI* / V' (V' = Vnew, the end-of-step volume of step n)
+    T Is[APL];
+    const T *Ist = (const T *)a.I_star_in + row;
+    ang.read_lane(Ist + ang.k[0], Ist + k_single, Is);
+    rt_source_vjp_cell<T, LPC, APL>(a, ang, cell, l, Is, Ic, Vnew);
   }
 
   {
@@ -241,13 +258,16 @@ hipError_t launch_mode(const rt_step_args &args, hipStream_t s) {
   const int64_t nblk = (a.N + cpb - 1) / cpb;
   const dim3 grid((unsigned)rt_grid_for(nblk)), block(RT_BLOCK);
   const size_t per = (a.do_transport == 2 ? 3 : 1) * sizeof(V4) + sizeof(int32_t);
-  const size_t smem = a.do_transport ? per * (size_t)a.hf_cap : 0;
+  const bool faces = a.do_transport >= 1 && a.do_transport <= 4;
+  const size_t smem = faces ? per * (size_t)a.hf_cap : 0;
   if (smem > (size_t)a.lds_max) return hipErrorInvalidConfiguration;
   switch (a.do_transport) {
     case 0: hipLaunchKernelGGL((k_step<T, LPC, APL, 0, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 1: hipLaunchKernelGGL((k_step<T, LPC, APL, 1, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 2: hipLaunchKernelGGL((k_step<T, LPC, APL, 2, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     case 3: hipLaunchKernelGGL((k_step<T, LPC, APL, 3, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
+    case 4: hipLaunchKernelGGL((k_step<T, LPC, APL, 4, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
+    case 5: hipLaunchKernelGGL((k_step<T, LPC, APL, 5, FULL, PAIRED>), grid, block, smem, s, a, nblk); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

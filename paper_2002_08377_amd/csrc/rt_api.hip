@@ -146,7 +146,7 @@ rt_step_args base_args(const rt_mesh *m, const rt_params *p, const rt_angles *a)
 // The transport part of a step; with `src` set, the source follows each stage.
 int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, double *vol,
              const double *rho, double *mom, double *etot, const double *kP, const double *kJ, const double *ks,
-             double *T_new, bool src, hipStream_t st, void *I_star = nullptr) {
+             double *T_new, bool src, hipStream_t st, void *I_star = nullptr, double *src_tape = nullptr) {
   rt_step_args s = base_args(m, p, a);
   s.rho = rho;
   s.mom = mom;
@@ -158,6 +158,7 @@ int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_i
     s.I_in = I_in;
     s.I_out = I_out;
     s.I_star_out = I_star;
+    s.src_tape_out = src_tape;
     s.vol_in = vol;
     s.vol_out = vol;
     s.T_out = T_new;
@@ -490,15 +491,17 @@ int rt_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in
 
 int rt_step_taped(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_in, void *I_out, void *I_star,
                   double *vol, const double *rho, double *mom, double *etot, const double *kP, const double *kJ,
-                  const double *ks, double *T_new, void *stream) {
+                  const double *ks, double *T_new, double *src_tape, void *stream) {
   int rc = check_call(m, p, a);
   if (rc) return rc;
   if ((rc = check_ptrs({I_in, I_out, I_star, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
   if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "rt_step_taped covers RT_UPWIND1 steps only");
+  if (src_tape && !aligned8(src_tape)) return fail(RT_EINVAL, "src_tape is not 8-byte aligned");
   const size_t bytes = elem(p->dtype) * m->N * a->K;
   if (overlap(I_in, I_out, bytes) || overlap(I_in, I_star, bytes) || overlap(I_out, I_star, bytes))
     return fail(RT_EINVAL, "I_in, I_out and I_star must not overlap");
-  return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream, I_star);
+  return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream, I_star,
+                  src_tape);
 }
 
 int rt_gradient(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I, void *grad, void *stream) {
@@ -561,6 +564,71 @@ int rt_step_adjoint(rt_mesh *m, const rt_params *p, const rt_angles *a, const vo
   t.do_source = 0;
   t.write_gas = 0;
   e = rt_launch_step(t, p->dtype, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint transport kernel launch");
+  return RT_OK;
+}
+
+int rt_step_adjoint_run(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t n_steps,
+                        const void *const *I_star, const double *const *src_tape, const double *const *vol_n,
+                        const double *const *mom_n, const double *rho, const double *kP, const double *kJ,
+                        const double *ks, void *lamI, double *lamE, double *lamM, double *dkP, double *dkJ,
+                        void *stream) {
+  int rc = check_call(m, p, a);
+  if (rc) return rc;
+  if (n_steps < 0) return fail(RT_EINVAL, "n_steps < 0");
+  if (n_steps == 0) return RT_OK;
+  if ((rc = check_ptrs({rho, kP, kJ, ks, lamI, lamE, lamM}))) return rc;
+  if (!I_star || !src_tape || !vol_n || !mom_n) return fail(RT_EINVAL, "a per-step pointer array is NULL");
+  for (int32_t i = 0; i < n_steps; ++i) {
+    if ((rc = check_ptrs({I_star[i], src_tape[i], vol_n[i], mom_n[i]}))) return rc;
+    if (!aligned8(src_tape[i])) return fail(RT_EINVAL, "src_tape[%d] is not 8-byte aligned", i);
+  }
+  if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "the adjoint covers RT_UPWIND1 steps only");
+  if (!(m->flags & RT_MESH_ADJOINT)) return fail(RT_ESTATE, "rt_step_adjoint_run needs RT_MESH_ADJOINT");
+  const size_t bytes = elem(p->dtype) * m->N * a->K;
+  for (int32_t i = 0; i < n_steps; ++i)
+    if (overlap(I_star[i], lamI, bytes)) return fail(RT_EINVAL, "I_star[%d] overlaps lamI", i);
+  const hipStream_t st = (hipStream_t)stream;
+  // The reverse chain alternates between lamI and the mesh's adjoint buffer: every launch
+  // after the first gathers its neighbours' rows from the previous launch's output, so it
+  // writes the other buffer.  The first launch (per cell, in place allowed) picks its
+  // buffer so that the last one, the transpose of step 0, writes lamI.
+  void *buf[2] = {lamI, m->lam_star};
+  int out = n_steps % 2;  // the buffer the first launch writes (lamI in place when 0)
+  rt_step_args s = base_args(m, p, a);
+  s.rho = rho;
+  s.kP = kP;
+  s.kJ = kJ;
+  s.ks = ks;
+  s.lamE = lamE;
+  s.lamM = lamM;
+  s.dkP = dkP;
+  s.dkJ = dkJ;
+  s.do_source = 0;
+  s.write_gas = 0;
+  for (int32_t n = n_steps - 1; n >= 0; --n) {
+    // n = n_steps - 1: the source reverse of the last step; below it, the transpose of step
+    // n + 1 fused with the source reverse of step n
+    const bool first = n == n_steps - 1;
+    rt_step_args t = s;
+    t.I_in = first ? lamI : buf[out];
+    if (!first) out = 1 - out;
+    t.I_out = buf[out];
+    t.I_star_in = I_star[n];
+    t.src_tape = src_tape[n];
+    t.vol_in = vol_n[n];
+    t.mom = const_cast<double *>(mom_n[n]);  // read only in these modes
+    t.do_transport = first ? 5 : 4;
+    hipError_t e = rt_launch_step(t, p->dtype, st);
+    if (e != hipSuccess) return hip_fail(e, first ? "source reverse launch" : "fused adjoint launch");
+  }
+  // the transpose of step 0 (start-of-step volume V^0) into lamI
+  rt_step_args t = s;
+  t.I_in = buf[out];
+  t.I_out = lamI;
+  t.vol_in = vol_n[0];
+  t.do_transport = 3;
+  hipError_t e = rt_launch_step(t, p->dtype, st);
   if (e != hipSuccess) return hip_fail(e, "adjoint transport kernel launch");
   return RT_OK;
 }

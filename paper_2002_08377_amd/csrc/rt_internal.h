@@ -74,6 +74,13 @@ struct rt_step_args {
   const double *kJ;
   const double *ks;
   double *T_out;
+  double *src_tape_out;  // taped upwind step: per-cell source values for the reverse
+                         // ([N][RT_SRC_TAPE]), written when set
+  // modes 4 and 5 (reverse of the source of step n)
+  const void *I_star_in;    // I* of step n
+  const double *src_tape;   // its source tape
+  double *lamE, *lamM;      // dL/d(E_g, m)^{n+1} in, dL/d(E_g, m)^n out
+  double *dkP, *dkJ;        // incremented when set (may be one array)
   double c_red, c_light, a_rad, cv, dt;
   double inv_c;       // 1 / c
   double e_gain;      // 4 pi c / cbar: gas energy per unit of sum W (I - I')
@@ -86,7 +93,8 @@ struct rt_step_args {
   const uint8_t *wg_order16, *wg_order32, *wg_order64;  // cell order within workgroups
   const uint8_t *wg_order;                              // the one of the launched kernel
   int do_transport;  // 0: source only (in place), 1: upwind, 2: reconstructed (PLM stage 2),
-                     // 3: transpose of upwind transport (adjoint)
+                     // 3: transpose of upwind transport (adjoint), 4: transpose of step n + 1
+                     // then the source reverse of step n, 5: source reverse of step n only
   int do_source;
   int write_gas;
 };

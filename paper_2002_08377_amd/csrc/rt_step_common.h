@@ -208,5 +208,14 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
         a.mom[3 * cell + 2] = m2 + a.m_gain * dFz;
       }
       if (a.T_out) a.T_out[cell] = Tnew;
+      if (a.src_tape_out) {
+        double *tp = a.src_tape_out + RT_SRC_TAPE * cell;
+        tp[0] = iQ;
+        tp[1] = S1;
+        tp[2] = SG;
+        tp[3] = SI;
+        tp[4] = iD;
+        tp[5] = Tnew;
+      }
     }
   }

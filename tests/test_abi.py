@@ -63,6 +63,7 @@ def test_calls_reject_null_mesh():
     rc = L.rt_step(None, ctypes.byref(prm), None, *([None] * 11))
     assert rc == rt.RT_EINVAL
     for name in ("rt_transport_step", "rt_source_implicit", "rt_step_taped", "rt_gradient", "rt_step_adjoint",
+                 "rt_step_adjoint_run",
                  "rt_flux_loss", "rt_moments", "rt_diagnostics", "rt_source_implicit_mg", "rt_step_mg",
                  "rt_source_implicit_kT", "rt_step_kT", "rt_marked_apply"):
         fn = getattr(L, name)

@@ -174,6 +174,91 @@ def test_adjoint_matches_oracle(regime, K, layout):
     assert e["L"] < 1e-12 and e["gI"] < 1e-10 and e["gk"] < 1e-10
 
 
+def _taped_run(dp, steps):
+    """`steps` taped steps with source tapes; the per-step records and the loss seed."""
+    N = dp.I.shape[0]
+    rec = []
+    for _ in range(steps):
+        vol_n, mom_n, etot_n = dp.vol.clone(), dp.mom.clone(), dp.etot.clone()
+        Istar = torch.empty_like(dp.I)
+        tape = torch.full((N, rt.SRC_TAPE), float("nan"), dtype=torch.float64, device="cuda")
+        rt.step_taped(dp.mesh, dp.params, dp.angles, dp.I, dp.I2, Istar, dp.vol, dp.rho, dp.mom, dp.etot, dp.kP,
+                      dp.kJ, dp.ks, src_tape=tape)
+        rec.append((Istar, tape, vol_n, mom_n, etot_n))
+        dp.I, dp.I2 = dp.I2, dp.I
+    return rec
+
+
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("K,layout,steps", [(24, None, 4), (24, ADJ, 3), (80, None, 3), (80, ADJ, 4),
+                                            (120, None, 4), (80, None, 1)])
+@pytest.mark.parametrize("regime", RG)
+def test_adjoint_run_matches_oracle(regime, K, layout, steps, dtype):
+    """The run adjoint (source reverse of the last step, then the transpose of each step fused
+    with the source reverse of the step before it, then the transpose of step 0; the source
+    reverse reading the forward's taped sums and temperature) against the oracle's reverse
+    mode: paired layouts (K = 24: 4 lanes x 6, K = 80: 8 x 10; antipodes K/2 apart or side by
+    side) and the general one (K = 120), odd and even step counts (the chain ends in either
+    of its two buffers).  FP64 within 1e-10 of the oracle; its energy and momentum adjoints
+    within 1e-12 of the per-step adjoint's.  FP32 within 1e-5 (intensity gradient) and 1e-4
+    (opacity gradient), as the checkpointed FP32 gradient."""
+    p, _ = _order(regime_problem(regime, index=2, n=8, K=K, steps=steps), layout)
+    st = p.state
+    dp = DeviceProblem(p, dtype=dtype, flags=rt.MESH_ADJOINT)
+    rec = _taped_run(dp, steps)
+    u = inp.loss_face_weights(p.mesh, np.random.default_rng(9))
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    seed = torch.zeros_like(dp.I)
+    rt.flux_loss(dp.mesh, dp.params, dp.angles, dp.I, _d(u), loss, seed)
+    lamI, lamE, lamM, dk = seed.clone(), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom), torch.zeros_like(dp.kP)
+    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [r[0] for r in rec], [r[1] for r in rec],
+                        [r[2] for r in rec], [r[3] for r in rec], dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM, dk, dk)
+    # the per-step adjoint on the same records
+    lamI2, lamE2, lamM2, dk2 = seed.clone(), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom), torch.zeros_like(dp.kP)
+    for I_star, _, vol_n, mom_n, etot_n in reversed(rec):
+        rt.step_adjoint(dp.mesh, dp.params, dp.angles, I_star, vol_n, dp.rho, mom_n, etot_n, dp.kP, dp.kJ, dp.ks,
+                        lamI2, lamE2, lamM2, dk2, dk2)
+    torch.cuda.synchronize()
+    Lo, gI, gk = orc.adjoint(dp.om, p.dirs, p.weights, p.phys, p.dt, dp.oracle_state(), st.rho, st.kP, st.ks,
+                             steps, u)
+    e = dict(gI=rel_err(lamI.double().cpu().numpy(), gI), gk=rel_err(dk.cpu().numpy(), gk),
+             E_vs_step=rel_err(lamE.cpu().numpy(), lamE2.cpu().numpy()),
+             M_vs_step=rel_err(lamM.cpu().numpy(), lamM2.cpu().numpy()))
+    print(regime, K, layout, steps, dtype, e)
+    if dtype == rt.F64:
+        assert e["gI"] < 1e-10 and e["gk"] < 1e-10, e
+        assert e["E_vs_step"] < 1e-12 and e["M_vs_step"] < 1e-12, e
+    else:
+        assert e["gI"] < 1e-5 and e["gk"] < 1e-4, e
+
+
+def test_adjoint_run_refuses_bad_records():
+    p = regime_problem("c", index=2, n=6, K=24, steps=2)
+    dp = DeviceProblem(p, flags=rt.MESH_ADJOINT)
+    rec = _taped_run(dp, 2)
+    lamI, lamE, lamM = torch.zeros_like(dp.I), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom)
+    args = lambda r: ([x[0] for x in r], [x[1] for x in r], [x[2] for x in r], [x[3] for x in r])
+    # I_star of a step overlapping lamI
+    with pytest.raises(rt.RTError) as e:
+        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, *args(rec), dp.rho, dp.kP, dp.kJ, dp.ks, rec[1][0],
+                            lamE, lamM)
+    assert e.value.code == rt.RT_EINVAL
+    # without the adjoint buffer
+    plain = DeviceProblem(p)
+    with pytest.raises(rt.RTError) as e:
+        rt.step_adjoint_run(plain.mesh, plain.params, plain.angles, *args(rec), dp.rho, dp.kP, dp.kJ, dp.ks, lamI,
+                            lamE, lamM)
+    assert e.value.code == rt.RT_ESTATE
+    # mismatched record lists are refused by the binding; zero steps leave the adjoints alone
+    with pytest.raises(ValueError):
+        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [rec[0][0]], [], [], [], dp.rho, dp.kP, dp.kJ, dp.ks,
+                            lamI, lamE, lamM)
+    lamI.fill_(2.0)
+    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [], [], [], [], dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM)
+    torch.cuda.synchronize()
+    assert bool((lamI == 2.0).all())
+
+
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 @pytest.mark.parametrize("regime", RG)
 def test_autograd_gradient_matches_oracle(regime, dtype):
