@@ -177,7 +177,7 @@ __global__ __launch_bounds__(RT_BLOCK) void k_source_vjp(rt_adj_args a, int64_t 
   lv[1] = rt_group_sum<LPC>(lv[1]);
   lv[2] = rt_group_sum<LPC>(lv[2]);
   // the transport adjoint takes dL/dI* per unit of charge: lam* / V'
-  const double iVp = rt_rcp(a.vol_n[cell] + dt * a.D[cell]);
+  const double iVp = rt_rcp(rt_vol_next(a.vol_n[cell], dt, a.D[cell]));
   T *LS = (T *)a.lam_star;
 #pragma unroll
   for (int q = 0; q < APL; ++q)

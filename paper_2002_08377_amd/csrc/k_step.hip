@@ -93,12 +93,12 @@ k_step(rt_step_args a, int64_t nblk) {
   ang.read_lane(Iin_lane + row, Iin_single + row, Ic);
 
   double Vnew = 0.0;
-  if (MODE == 5) Vnew = a.vol_in[cell] + a.dt * a.D[cell];
+  if (MODE == 5) Vnew = rt_vol_next(a.vol_in[cell], a.dt, a.D[cell]);
   if (FACES) {
     // ---- transport: charges V I minus the upwind charge through every face -------------
     const double Vn = a.vol_in[cell];
     const double dV = a.dt * a.D[cell];
-    Vnew = Vn + dV;  // the end-of-step volume, formed as the forward step forms it
+    Vnew = rt_vol_next(Vn, a.dt, a.D[cell]);  // the end-of-step volume
     // the charge through the faces is accumulated apart from V I (the transpose adds V mu,
     // with V the start-of-step volume of the step it transposes: step n + 1 in mode 4)
     T acc[APL];

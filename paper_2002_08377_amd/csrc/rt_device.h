@@ -117,6 +117,10 @@ __device__ __forceinline__ double rt_rcp(double x) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float rt_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// The end-of-step volume V' = V + dt D of the volume update (section 2.2), formed by every
+// kernel as one fused multiply-add: left to the compiler, the sum is contracted in some
+// kernels and not in others, and a step and its reverse then disagree in the last bit.
+__device__ __forceinline__ double rt_vol_next(double V, double dt, double D) { return fma(dt, D, V); }
 // Reciprocal within an ulp in either precision (FP32: the estimate refined by one
 // Newton step), for ratios that decide a limiter.
 __device__ __forceinline__ double rt_rcp_refined(double x) { return rt_rcp(x); }

@@ -25,7 +25,7 @@ import pytest
 import torch
 
 import oracle as orc
-from gpu_helpers import elem_err, rel_err
+from gpu_helpers import elem_err, regime_problem, rel_err
 from paper_2002_08377_amd import inputs as inp
 from paper_2002_08377_amd import rt
 from paper_2002_08377_amd.autograd import RTSystem, flux_loss, rt_steps
@@ -158,17 +158,28 @@ def test_gradient_matches_oracle():
     assert rel_err(gk.cpu().numpy(), gko) < 1e-10
 
 
+@pytest.mark.parametrize("fast", [False, True])
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-def test_checkpoint_interval_leaves_gradients_unchanged(dtype):
-    p = inp.make_problem(2, n=8, K=48, steps=7)
+def test_checkpoint_interval_leaves_gradients_unchanged(dtype, fast):
+    """Bitwise the same gradients for every checkpoint interval, with the backward pass's
+    recompute overlapped on a second stream or not (7 steps: 1 to 7 segments, odd and even
+    counts, a short last segment).  The segment boundaries take the end-of-step volumes from
+    the forward's records, the fused reverse forms them itself: with faces moving at ~0.3 cbar
+    (every volume changing by a large fraction of an ulp's worth of dt D per step) the two
+    must still agree bit for bit."""
+    p = (regime_problem("reduced_fast", index=2, n=8, K=48, steps=7) if fast
+         else inp.make_problem(2, n=8, K=48, steps=7))
     system, x = _system(p, dtype)
     fw = _d(inp.loss_face_weights(p.mesh, np.random.default_rng(5)))
+    system.overlap = False
     ref = _grads(system, x, fw, p.steps, 1)
-    for ckpt in (2, 3, 7, 10):
-        got = _grads(system, x, fw, p.steps, ckpt)
-        assert got[0] == ref[0]
-        for a, b in zip(got[1:], ref[1:]):
-            assert torch.equal(a, b), ckpt
+    for overlap in (False, True):
+        system.overlap = overlap
+        for ckpt in (1, 2, 3, 7, 10):
+            got = _grads(system, x, fw, p.steps, ckpt)
+            assert got[0] == ref[0]
+            for a, b in zip(got[1:], ref[1:]):
+                assert torch.equal(a, b), (ckpt, overlap)
 
 
 def test_all_input_gradients_match_directional_differences():
