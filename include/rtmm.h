@@ -70,7 +70,7 @@ enum {
 
 #define RT_K_MAX 128
 #define RT_NDIAG 10
-#define RT_SRC_TAPE 6 /* doubles per cell of a source tape (rt_step_taped, rt_step_adjoint_run) */
+#define RT_SRC_TAPE 10 /* doubles per cell of a source tape (rt_step_taped, rt_step_adjoint_run) */
 
 typedef struct rt_mesh rt_mesh;
 typedef struct rt_marked rt_marked;
@@ -227,16 +227,18 @@ int rt_step(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, con
 
 /*
  * One RT_UPWIND1 step as rt_step (transport, section 2.2, then the source,
- * section 2.3, in one fused pass) that also stores the transported intensities,
- * i.e. the source's input, in I_star [N][K] (device, dtype): the value
- * rt_step_adjoint needs for this step.  When src_tape [N][RT_SRC_TAPE] (device,
- * double, nullable) is given, it receives per cell the values of the source solve
- * (section 2.3, steps 1-2) that rt_step_adjoint_run reuses instead of solving again:
- * 1 / sum_k W_k Gamma_k^-2, the weighted sums S1 = sum Wt r, SG = sum Wt Gamma r,
- * SI = sum Wt Gamma^4 I* r (Wt = W Gamma^-2 / that sum, r = 1 / (1 + y chi Gamma)),
- * 1 / (S1 + y kJ SG), and the new temperature T^{n+1}.  I_out and vol, mom, etot, T_new
- * receive exactly what rt_step gives.  I_in, I_out and I_star must not overlap.
- * RT_EINVAL for RT_PLM_VL2.
+ * section 2.3, in one fused pass) that also records what a reverse of the step needs.
+ * I_star [N][K] (device, dtype, nullable) receives the transported intensities, i.e.
+ * the source's input: the value rt_step_adjoint needs for this step.  src_tape
+ * [N][RT_SRC_TAPE] (device, double, nullable) receives per cell what
+ * rt_step_adjoint_run needs of this step besides its output I_out: the values of the
+ * source solve (section 2.3, steps 1-2)
+ * that it reuses instead of solving again, 1 / sum_k W_k Gamma_k^-2, the weighted sums
+ * S1 = sum Wt r, SG = sum Wt Gamma r, SI = sum Wt Gamma^4 I* r (Wt = W Gamma^-2 / that
+ * sum, r = 1 / (1 + y chi Gamma)), 1 / (S1 + y kJ SG) and the new temperature T^{n+1};
+ * then the start-of-step volume V^n and gas momentum (rho v)^n (3 values).  At least
+ * one of the two must be given.  I_out and vol, mom, etot, T_new receive exactly what
+ * rt_step gives.  I_in, I_out and I_star must not overlap.  RT_EINVAL for RT_PLM_VL2.
  */
 int rt_step_taped(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I_in, void *I_out,
                   void *I_star, double *vol, const double *rho, double *mom, double *etot, const double *kP,
@@ -282,23 +284,24 @@ int rt_step_adjoint(rt_mesh *mesh, const rt_params *params, const rt_angles *ang
  * but the first and last transposes the transport of step n + 1 and reverses the
  * source of step n in one pass, so dL/dI between them never goes to memory, and the
  * source reverse reads the forward's own sums and temperature from the tape
- * (section 2.3; through the temperature root by the implicit function theorem).
- * I_star, src_tape, vol_n, mom_n: host arrays of n_steps device pointers; entry i
- * belongs to step i of the run: its transported intensities and source tape (the
- * I_star and src_tape outputs of its rt_step_taped call), and the volume [N] and gas
- * momentum [N][3] before it.  The gas energy is not needed.  rho, kP, kJ, ks as in the
- * forward steps.  lamI [N][K] (dtype) holds dL/dI after the last step on entry and
+ * (section 2.3; through the temperature root by the implicit function theorem).  It
+ * reads each step's output, not its transported intensities: the source update
+ * inverts to Gamma^4 I* + y Gamma S = I' Gamma^4 / r, so the forward need not store I*.
+ * I_next, src_tape: host arrays of n_steps device pointers; entry i belongs to step i
+ * of the run: its output intensities (the I_out of its rt_step_taped call, kept
+ * unchanged) and its source tape (which holds the step's start-of-step volume and
+ * momentum, so no other state is needed).  rho, kP, kJ, ks as in the forward steps.  lamI [N][K] (dtype) holds dL/dI after the last step on entry and
  * dL/dI before step 0 on return; lamE, lamM, dL_dkP, dL_dkJ as in rt_step_adjoint.
  * Uses the mesh's RT_MESH_ADJOINT buffer (RT_ESTATE without it), so calls on one mesh
  * are serialised by their stream.  n_steps = 0 does nothing.  A NULL entry, an
- * I_star[i] overlapping lamI or a misaligned tape give RT_EINVAL before any launch;
- * after a failed launch the adjoints hold unspecified values.
+ * I_next[i] overlapping lamI or the mesh's adjoint buffer, or a misaligned tape give
+ * RT_EINVAL before any launch; after a failed launch the adjoints hold unspecified
+ * values.
  */
 int rt_step_adjoint_run(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, int32_t n_steps,
-                        const void *const *I_star, const double *const *src_tape, const double *const *vol_n,
-                        const double *const *mom_n, const double *rho, const double *kP, const double *kJ,
-                        const double *ks, void *lamI, double *lamE, double *lamM, double *dL_dkP,
-                        double *dL_dkJ, void *stream);
+                        const void *const *I_next, const double *const *src_tape, const double *rho,
+                        const double *kP, const double *kJ, const double *ks, void *lamI, double *lamE,
+                        double *lamM, double *dL_dkP, double *dL_dkJ, void *stream);
 
 /*
  * Emergent-flux loss L = sum_f u_f A_f 4 pi c sum_k W_k (n_k.n_f) I_up(f,k),

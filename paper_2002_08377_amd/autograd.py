@@ -5,9 +5,9 @@ sections 2.2-2.3) with the fused step call and keeps a checkpoint of the state
 (I, E_g, rho v, V) at the start of every segment of `ckpt_every` steps.  The
 backward pass walks the segments in reverse: it restores the segment's
 checkpoint, re-runs its steps with the taped step call (the same fused kernel,
-so the same values bit for bit, which also stores the transported intensities
-I* and the per-cell sums and temperature of the source solve), records the
-start-of-step volume and gas state, and then reverses the segment's steps with
+so the same values bit for bit, each step's output kept in a buffer of its own,
+which also stores a per-cell tape: the sums and temperature of the source solve,
+the start-of-step volume and momentum), and then reverses the segment's steps with
 one run-adjoint call (the transpose of each step fused with the source reverse of
 the step before it).  The last segment is taped during the forward pass already
 (the backward starts there), so it is not run again.  Peak memory is therefore one
@@ -61,14 +61,9 @@ def _gas_views(gas):
 
 
 def _record(N, dev):
-    """One step's record: the start-of-step gas state (as _gas_views) followed by the
-    step's source tape [N, SRC_TAPE], in one FP64 buffer."""
-    return torch.empty((5 + rt.SRC_TAPE) * N, dtype=torch.float64, device=dev)
-
-
-def _record_views(rec):
-    N = rec.shape[0] // (5 + rt.SRC_TAPE)
-    return rec[:5 * N], rec[5 * N:].view(N, rt.SRC_TAPE)
+    """One step's source tape: what the reverse needs of the step besides I* (the source
+    solve's sums and temperature, the start-of-step volume and momentum)."""
+    return torch.empty((N, rt.SRC_TAPE), dtype=torch.float64, device=dev)
 
 
 class RTSteps(torch.autograd.Function):
@@ -100,29 +95,31 @@ class RTSteps(torch.autograd.Function):
             if n % ckpt_every == 0 and n < last:  # the last segment is taped instead
                 ckpts.append((I.clone(), gas.clone()))
             if n >= last:
-                # the last segment: tape it now (the taped step gives the fused step's values)
+                # the last segment: tape it now (the taped step gives the fused step's values),
+                # each step's output in a buffer of its own, kept for the reverse
                 rec = (torch.empty_like(I), _record(I.shape[0], I.device))
-                g_n, src = _record_views(rec[1])
-                g_n.copy_(gas)
-                rt.step_taped(system.mesh, system.params, system.angles, I, I2, rec[0], vol, system.rho, mom, etot,
-                              kap, kap, system.ks, src_tape=src)
+                rt.step_taped(system.mesh, system.params, system.angles, I, rec[0], None, vol, system.rho, mom,
+                              etot, kap, kap, system.ks, src_tape=rec[1])
                 tape.append(rec)
+                I = rec[0]
             else:
                 rt.step(system.mesh, system.params, system.angles, I, I2, vol, system.rho, mom, etot, kap, kap,
                         system.ks)
-            I, I2 = I2, I
+                I, I2 = I2, I
         ctx.system = system
         ctx.n_steps = n_steps
         ctx.ckpt_every = ckpt_every
         ctx.ckpts = ckpts
         ctx.last_tape = tape
-        ctx.save_for_backward(kap)
+        # the returned intensities are the last step's record: saving them makes autograd refuse
+        # a backward pass after they were changed in place
+        ctx.save_for_backward(kap, I)
         ctx.in_dtype = I0.dtype
         return I, etot.clone(), mom.clone()
 
     @staticmethod
     def backward(ctx, gI, gE, gM):
-        (kap,) = ctx.saved_tensors
+        kap, _ = ctx.saved_tensors
         s = ctx.system
         td = rt.torch_dtype(s.params.dtype)
         N, K = s.mesh.n_cells, s.angles.K
@@ -148,28 +145,26 @@ class RTSteps(torch.autograd.Function):
         sets = []
         for k in range(nsets):
             # the forward pass's records of the last segment are reused for recomputed segments
-            # once that segment's reverse (enqueued first) has read them
-            tI = [rec[0] for rec in ctx.last_tape] if k == last_set else []
+            # once that segment's reverse (enqueued first) has read them; not its last output,
+            # which the caller holds
+            tI = [rec[0] for rec in ctx.last_tape[:-1]] if k == last_set else []
             tR = [rec[1] for rec in ctx.last_tape] if k == last_set else []
             tI += [torch.empty((N, K), dtype=td, device=dev) for _ in range(m - len(tI))]
             tR += [_record(N, dev) for _ in range(m - len(tR))]
             sets.append((tI, tR))
-        I2 = torch.empty((N, K), dtype=td, device=dev)
 
         def recompute(seg):
-            """Enqueue the taped recompute of segment `seg` on the current stream."""
+            """Enqueue the taped recompute of segment `seg` on the current stream: each step
+            writes its output into the next record buffer, where the reverse reads it."""
             tI, tR = sets[seg % nsets]
-            # each checkpoint is read once, so the recompute steps in its own buffers
-            I, gas = ctx.ckpts[seg]
+            # each checkpoint is read once, so the recompute starts from its own buffers
+            cur, gas = ctx.ckpts[seg]
             vol, mom, etot = _gas_views(gas)
-            cur, nxt = I, I2
             tape = []
             for n in range(min(L, ctx.n_steps - seg * L)):
-                g_n, src = _record_views(tR[n])
-                g_n.copy_(gas)
-                rt.step_taped(s.mesh, s.params, s.angles, cur, nxt, tI[n], vol, s.rho, mom, etot, kap, kap, s.ks,
-                              src_tape=src)
-                cur, nxt = nxt, cur
+                rt.step_taped(s.mesh, s.params, s.angles, cur, tI[n], None, vol, s.rho, mom, etot, kap, kap, s.ks,
+                              src_tape=tR[n])
+                cur = tI[n]
                 tape.append((tI[n], tR[n]))
             return tape
 
@@ -192,10 +187,8 @@ class RTSteps(torch.autograd.Function):
                 main.wait_event(ev)
             else:
                 tape = recompute(seg)  # after the reverse of seg + 1 has read the one record set
-            views = [(_gas_views(_record_views(r)[0]), _record_views(r)[1]) for _, r in tape]
-            rt.step_adjoint_run(s.mesh, s.params, s.angles, [i for i, _ in tape], [v[1] for v in views],
-                                [v[0][0] for v in views], [v[0][1] for v in views], s.rho, kap, kap, s.ks,
-                                lamI, lamE, lamM, dk, dk, stream=main)
+            rt.step_adjoint_run(s.mesh, s.params, s.angles, [i for i, _ in tape], [r for _, r in tape], s.rho,
+                                kap, kap, s.ks, lamI, lamE, lamM, dk, dk, stream=main)
             ev = torch.cuda.Event()
             ev.record(main)
             reversed_ev[seg] = ev

@@ -92,11 +92,15 @@ k_step(rt_step_args a, int64_t nblk) {
   T Ic[APL];
   ang.read_lane(Iin_lane + row, Iin_single + row, Ic);
 
-  double Vnew = 0.0;
-  if (MODE == 5) Vnew = rt_vol_next(a.vol_in[cell], a.dt, a.D[cell]);
+  double Vnew = 0.0, Vstart = 0.0;
+  // the start-of-step volume: the reverse modes take it from the forward step's tape
+  const double *tape = a.src_tape ? a.src_tape + RT_SRC_TAPE * cell : nullptr;
+  const bool vol_from_tape = MODE >= 4 || (MODE == 3 && tape);
+  if (MODE == 5) Vnew = rt_vol_next(tape[RT_TAPE_V], a.dt, a.D[cell]);
   if (FACES) {
     // ---- transport: charges V I minus the upwind charge through every face -------------
-    const double Vn = a.vol_in[cell];
+    const double Vn = vol_from_tape ? tape[RT_TAPE_V] : a.vol_in[cell];
+    Vstart = Vn;
     const double dV = a.dt * a.D[cell];
     Vnew = rt_vol_next(Vn, a.dt, a.D[cell]);  // the end-of-step volume
     // the charge through the faces is accumulated apart from V I (the transpose adds V mu,
@@ -230,11 +234,11 @@ k_step(rt_step_args a, int64_t nblk) {
   }
   if constexpr (MODE >= 4) {
     // Ic holds dL/dI^{n+1} of the cell; the reverse of the source of step n turns it into
-    // dL/dI* / V' (V' = Vnew, the end-of-step volume of step n)
-    T Is[APL];
-    const T *Ist = (const T *)a.I_star_in + row;
-    ang.read_lane(Ist + ang.k[0], Ist + k_single, Is);
-    rt_source_vjp_cell<T, LPC, APL>(a, ang, cell, l, Is, Ic, Vnew);
+    // dL/dI* / V' (V' = Vnew, the end-of-step volume of step n), reading the step's output
+    T Io[APL];
+    const T *In = (const T *)a.I_next + row;
+    ang.read_lane(In + ang.k[0], In + k_single, Io);
+    rt_source_vjp_cell<T, LPC, APL>(a, ang, cell, l, Io, Ic, Vnew);
   }
 
   {
@@ -242,6 +246,7 @@ k_step(rt_step_args a, int64_t nblk) {
     ang.write_lane(o + ang.k[0], o + k_single, Ic);
   }
   if ((MODE == 1 || MODE == 2) && l == 0 && a.vol_out) a.vol_out[cell] = Vnew;
+  if (MODE == 1 && l == 0 && a.src_tape_out) a.src_tape_out[RT_SRC_TAPE * cell + RT_TAPE_V] = Vstart;
 }
 
 // Staging needs (records per half-face) x (half-faces of the largest range of the

@@ -494,11 +494,13 @@ int rt_step_taped(rt_mesh *m, const rt_params *p, const rt_angles *a, const void
                   const double *ks, double *T_new, double *src_tape, void *stream) {
   int rc = check_call(m, p, a);
   if (rc) return rc;
-  if ((rc = check_ptrs({I_in, I_out, I_star, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
+  if ((rc = check_ptrs({I_in, I_out, vol, rho, mom, etot, kP, kJ, ks}))) return rc;
   if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "rt_step_taped covers RT_UPWIND1 steps only");
+  if (!I_star && !src_tape) return fail(RT_EINVAL, "rt_step_taped needs I_star or src_tape");
+  if (I_star && !aligned8(I_star)) return fail(RT_EINVAL, "I_star is not 8-byte aligned");
   if (src_tape && !aligned8(src_tape)) return fail(RT_EINVAL, "src_tape is not 8-byte aligned");
   const size_t bytes = elem(p->dtype) * m->N * a->K;
-  if (overlap(I_in, I_out, bytes) || overlap(I_in, I_star, bytes) || overlap(I_out, I_star, bytes))
+  if (overlap(I_in, I_out, bytes) || (I_star && (overlap(I_in, I_star, bytes) || overlap(I_out, I_star, bytes))))
     return fail(RT_EINVAL, "I_in, I_out and I_star must not overlap");
   return run_step(m, p, a, I_in, I_out, vol, rho, mom, etot, kP, kJ, ks, T_new, true, (hipStream_t)stream, I_star,
                   src_tape);
@@ -569,25 +571,25 @@ int rt_step_adjoint(rt_mesh *m, const rt_params *p, const rt_angles *a, const vo
 }
 
 int rt_step_adjoint_run(rt_mesh *m, const rt_params *p, const rt_angles *a, int32_t n_steps,
-                        const void *const *I_star, const double *const *src_tape, const double *const *vol_n,
-                        const double *const *mom_n, const double *rho, const double *kP, const double *kJ,
-                        const double *ks, void *lamI, double *lamE, double *lamM, double *dkP, double *dkJ,
-                        void *stream) {
+                        const void *const *I_next, const double *const *src_tape, const double *rho,
+                        const double *kP, const double *kJ, const double *ks, void *lamI, double *lamE,
+                        double *lamM, double *dkP, double *dkJ, void *stream) {
   int rc = check_call(m, p, a);
   if (rc) return rc;
   if (n_steps < 0) return fail(RT_EINVAL, "n_steps < 0");
   if (n_steps == 0) return RT_OK;
   if ((rc = check_ptrs({rho, kP, kJ, ks, lamI, lamE, lamM}))) return rc;
-  if (!I_star || !src_tape || !vol_n || !mom_n) return fail(RT_EINVAL, "a per-step pointer array is NULL");
+  if (!I_next || !src_tape) return fail(RT_EINVAL, "a per-step pointer array is NULL");
   for (int32_t i = 0; i < n_steps; ++i) {
-    if ((rc = check_ptrs({I_star[i], src_tape[i], vol_n[i], mom_n[i]}))) return rc;
+    if ((rc = check_ptrs({I_next[i], src_tape[i]}))) return rc;
     if (!aligned8(src_tape[i])) return fail(RT_EINVAL, "src_tape[%d] is not 8-byte aligned", i);
   }
   if (p->scheme != RT_UPWIND1) return fail(RT_EINVAL, "the adjoint covers RT_UPWIND1 steps only");
   if (!(m->flags & RT_MESH_ADJOINT)) return fail(RT_ESTATE, "rt_step_adjoint_run needs RT_MESH_ADJOINT");
   const size_t bytes = elem(p->dtype) * m->N * a->K;
   for (int32_t i = 0; i < n_steps; ++i)
-    if (overlap(I_star[i], lamI, bytes)) return fail(RT_EINVAL, "I_star[%d] overlaps lamI", i);
+    if (overlap(I_next[i], lamI, bytes) || overlap(I_next[i], m->lam_star, bytes))
+      return fail(RT_EINVAL, "I_next[%d] overlaps lamI or the mesh's adjoint buffer", i);
   const hipStream_t st = (hipStream_t)stream;
   // The reverse chain alternates between lamI and the mesh's adjoint buffer: every launch
   // after the first gathers its neighbours' rows from the previous launch's output, so it
@@ -614,19 +616,17 @@ int rt_step_adjoint_run(rt_mesh *m, const rt_params *p, const rt_angles *a, int3
     t.I_in = first ? lamI : buf[out];
     if (!first) out = 1 - out;
     t.I_out = buf[out];
-    t.I_star_in = I_star[n];
+    t.I_next = I_next[n];
     t.src_tape = src_tape[n];
-    t.vol_in = vol_n[n];
-    t.mom = const_cast<double *>(mom_n[n]);  // read only in these modes
     t.do_transport = first ? 5 : 4;
     hipError_t e = rt_launch_step(t, p->dtype, st);
     if (e != hipSuccess) return hip_fail(e, first ? "source reverse launch" : "fused adjoint launch");
   }
-  // the transpose of step 0 (start-of-step volume V^0) into lamI
+  // the transpose of step 0 (start-of-step volume V^0, from its tape) into lamI
   rt_step_args t = s;
   t.I_in = buf[out];
   t.I_out = lamI;
-  t.vol_in = vol_n[0];
+  t.src_tape = src_tape[0];
   t.do_transport = 3;
   hipError_t e = rt_launch_step(t, p->dtype, st);
   if (e != hipSuccess) return hip_fail(e, "adjoint transport kernel launch");

@@ -77,7 +77,7 @@ struct rt_step_args {
   double *src_tape_out;  // taped upwind step: per-cell source values for the reverse
                          // ([N][RT_SRC_TAPE]), written when set
   // modes 4 and 5 (reverse of the source of step n)
-  const void *I_star_in;    // I* of step n
+  const void *I_next;       // the output intensities of step n
   const double *src_tape;   // its source tape
   double *lamE, *lamM;      // dL/d(E_g, m)^{n+1} in, dL/d(E_g, m)^n out
   double *dkP, *dkJ;        // incremented when set (may be one array)
@@ -98,6 +98,12 @@ struct rt_step_args {
   int do_source;
   int write_gas;
 };
+
+// Per-cell values the taped forward step stores for the reverse ([N][RT_SRC_TAPE] doubles):
+// the source solve's 1 / sum W Gamma^-2, S1, SG, SI, 1 / D and T^{n+1}, then the
+// start-of-step volume and gas momentum (3).
+enum { RT_TAPE_IQ = 0, RT_TAPE_S1, RT_TAPE_SG, RT_TAPE_SI, RT_TAPE_ID, RT_TAPE_T, RT_TAPE_V, RT_TAPE_M };
+static_assert(RT_TAPE_M + 3 == RT_SRC_TAPE, "tape layout");
 
 hipError_t rt_launch_face_speed(const double *gen, const double *mesh_vel, const int32_t *face_cells,
                                 const int8_t *face_shift, const double *face_normal, const double *face_centroid,

@@ -8,8 +8,13 @@
 //   source S = kP a T^4 / 4 pi + ks J, per angle I'_k = (I0_k + y Gamma_k S) r_k Gamma_k^-4,
 //   then the gas takes the radiation energy and momentum the update removed (eqs. 35-36).
 // The taped forward step stores each cell's 1/sum W Gamma^-2, S1, SG, SI, 1/D and T^{n+1}
-// (D = S1 + y kJ SG), so the reverse needs no sums and no root of its own; through the root
+// (D = S1 + y kJ SG) with its start-of-step volume and momentum, so the reverse needs no
+// sums, no root and no gas state of its own; through the root
 // it uses the implicit function theorem, dT = -(T^4 dA + T dB - dC) / (4 A T^3 + B).
+//
+// The intensities the reverse reads are the step's output I' (which the recompute of a
+// segment keeps anyway, one buffer per step) rather than the transported I*: the update
+// inverts to Gamma^4 I* + y Gamma S = I' Gamma^4 / r, so the forward need not store I*.
 //
 // Per-angle arithmetic runs in the intensities' type T, sums over angles and per-cell
 // values in FP64, as in the forward source.  On return lam holds dL/dI* divided by the
@@ -18,18 +23,15 @@
 
 #include "rt_device.h"
 
-// Per-cell values the taped forward step stores for the reverse ([N][RT_SRC_TAPE] doubles).
-enum { RT_TAPE_IQ = 0, RT_TAPE_S1, RT_TAPE_SG, RT_TAPE_SI, RT_TAPE_ID, RT_TAPE_T };
-
 template <typename T, int LPC, int APL, typename Ang>
 __device__ __forceinline__ void rt_source_vjp_cell(const rt_step_args &a, const Ang &ang, int64_t cell, int l,
-                                                   const T (&Is)[APL], T (&lam)[APL], double Vp) {
+                                                   const T (&Io)[APL], T (&lam)[APL], double Vp) {
   constexpr int P = Ang::P;
   constexpr bool PAIRED = Ang::PAIRED_LAYOUT;
   const double rho = a.rho[cell];
-  const double m0 = a.mom[3 * cell], m1 = a.mom[3 * cell + 1], m2 = a.mom[3 * cell + 2];
   const double kP = a.kP[cell], kJ = a.kJ[cell], ks = a.ks[cell];
   const double *tp = a.src_tape + RT_SRC_TAPE * cell;
+  const double m0 = tp[RT_TAPE_M], m1 = tp[RT_TAPE_M + 1], m2 = tp[RT_TAPE_M + 2];
   const double iQ = tp[RT_TAPE_IQ], S1 = tp[RT_TAPE_S1], SG = tp[RT_TAPE_SG], SI = tp[RT_TAPE_SI];
   const double iD = tp[RT_TAPE_ID], Tq = tp[RT_TAPE_T];
   const double c = a.c_light, ic = a.inv_c, dt = a.dt;
@@ -54,7 +56,7 @@ __device__ __forceinline__ void rt_source_vjp_cell(const rt_step_args &a, const 
   const double lmp0 = a.lamM[3 * cell], lmp1 = a.lamM[3 * cell + 1], lmp2 = a.lamM[3 * cell + 2];
   const T clE = (T)(c * lEp), lm0 = (T)lmp0, lm1 = (T)lmp1, lm2 = (T)lmp2, mg = (T)a.m_gain;
 
-  // Between the passes a lane keeps only I*, the adjoint (dL/dI' net of the bookkeeping
+  // Between the passes a lane keeps only I', the adjoint (dL/dI' net of the bookkeeping
   // after the first pass, dL/dI* at the end), v.n / c per direction, and 1 / Gamma and r
   // per slot; each pass rebuilds the other forward quantities from them.  Empty register
   // barriers on the kept values make the rebuild real: without them the compiler holds
@@ -72,12 +74,16 @@ __device__ __forceinline__ void rt_source_vjp_cell(const rt_step_args &a, const 
     f.iG = first ? rt_rcp(f.G) : iGk[s];
     f.iG2 = f.iG * f.iG;
     f.iG4 = f.iG2 * f.iG2;
-    f.r = first ? rt_rcp(T(1) + ychiA * f.G) : rk[s];
+    const T den = T(1) + ychiA * f.G;  // 1 / r
+    f.r = first ? rt_rcp(den) : rk[s];
     iGk[s] = f.iG;
     rk[s] = f.r;
     const T G2 = f.G * f.G;
-    f.I0 = G2 * G2 * Is[s];
-    f.X = f.I0 + yA * f.G * SsA;
+    // X = Gamma^4 I* + y Gamma S from the step's output I' = X r / Gamma^4; Gamma^4 I* = X - y
+    // Gamma S cancels where the cell is optically thick (r << 1), but every use of it below is
+    // scaled by r again, so its absolute error stays at the rounding of I'
+    f.X = Io[s] * (G2 * G2) * den;
+    f.I0 = f.X - yA * f.G * SsA;
     return f;
   };
   auto through = [&](int s, T nl) { return (T)ang.wt(s) * mg * (clE + nl); };

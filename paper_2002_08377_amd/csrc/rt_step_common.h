@@ -210,12 +210,15 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
       if (a.T_out) a.T_out[cell] = Tnew;
       if (a.src_tape_out) {
         double *tp = a.src_tape_out + RT_SRC_TAPE * cell;
-        tp[0] = iQ;
-        tp[1] = S1;
-        tp[2] = SG;
-        tp[3] = SI;
-        tp[4] = iD;
-        tp[5] = Tnew;
+        tp[RT_TAPE_IQ] = iQ;
+        tp[RT_TAPE_S1] = S1;
+        tp[RT_TAPE_SG] = SG;
+        tp[RT_TAPE_SI] = SI;
+        tp[RT_TAPE_ID] = iD;
+        tp[RT_TAPE_T] = Tnew;
+        tp[RT_TAPE_M] = m0;  // the start-of-step momentum (the volume is written by the caller)
+        tp[RT_TAPE_M + 1] = m1;
+        tp[RT_TAPE_M + 2] = m2;
       }
     }
   }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "librtmm.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EHIP, RT_ENONFINITE, RT_ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32 = 0, 1
-SRC_TAPE = 6  # doubles per cell of a source tape (RT_SRC_TAPE)
+SRC_TAPE = 10  # doubles per cell of a source tape (RT_SRC_TAPE)
 UPWIND1, PLM_VL2 = 0, 1
 MESH_PLM, MESH_ADJOINT = 1, 2
 K_MAX = 128
@@ -63,7 +63,7 @@ _SIGS = {
     "rt_step_taped": [ctypes.c_void_p] * 16,
     "rt_gradient": [ctypes.c_void_p] * 6,
     "rt_step_adjoint": [ctypes.c_void_p] * 17,
-    "rt_step_adjoint_run": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 14,
+    "rt_step_adjoint_run": [ctypes.c_void_p] * 3 + [ctypes.c_int32] + [ctypes.c_void_p] * 12,
     "rt_flux_loss": [ctypes.c_void_p] * 8,
     "rt_flux_loss_noalloc": [ctypes.c_void_p] * 8,
     "rt_diagnostics": [ctypes.c_void_p] * 9,
@@ -386,7 +386,7 @@ def step_taped(mesh, params, angles, I_in, I_out, I_star, vol, rho, mom, etot, k
     N, K = _shapes(mesh, angles)
     td = torch_dtype(params.dtype)
     rc = lib().rt_step_taped(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), _dev(I_in, td, (N, K), "I_in"),
-                             _dev(I_out, td, (N, K), "I_out"), _dev(I_star, td, (N, K), "I_star"),
+                             _dev(I_out, td, (N, K), "I_out"), _dev(I_star, td, (N, K), "I_star", True),
                              _dev(vol, torch.float64, (N,), "vol"), *_gas(mesh, rho, mom, etot, kP, kJ, ks),
                              _dev(T_new, torch.float64, (N,), "T_new", True),
                              _dev(src_tape, torch.float64, (N, SRC_TAPE), "src_tape", True), _stream(stream))
@@ -416,21 +416,20 @@ def step_adjoint(mesh, params, angles, I_star, vol_n, rho, mom_n, etot_n, kP, kJ
     _check("rt_step_adjoint", rc)
 
 
-def step_adjoint_run(mesh, params, angles, I_star, src_tape, vol_n, mom_n, rho, kP, kJ, ks, lamI, lamE, lamM,
-                     dkP=None, dkJ=None, stream=None):
-    """Reverse of len(I_star) taped steps (lists of per-step tensors, entry i for step i)."""
+def step_adjoint_run(mesh, params, angles, I_next, src_tape, rho, kP, kJ, ks, lamI, lamE, lamM, dkP=None,
+                     dkJ=None, stream=None):
+    """Reverse of len(I_next) taped steps (lists of per-step tensors, entry i for step i: its
+    output intensities and its source tape)."""
     N, K = _shapes(mesh, angles)
     td = torch_dtype(params.dtype)
     f = torch.float64
-    n = len(I_star)
-    if not (len(src_tape) == len(vol_n) == len(mom_n) == n):
-        raise ValueError("I_star, src_tape, vol_n and mom_n need one entry per step")
+    n = len(I_next)
+    if len(src_tape) != n:
+        raise ValueError("I_next and src_tape need one entry per step")
     arr = lambda xs: (ctypes.c_void_p * max(n, 1))(*xs)
-    ps = arr([_dev(x, td, (N, K), f"I_star[{i}]") for i, x in enumerate(I_star)])
+    ps = arr([_dev(x, td, (N, K), f"I_next[{i}]") for i, x in enumerate(I_next)])
     pt = arr([_dev(x, f, (N, SRC_TAPE), f"src_tape[{i}]") for i, x in enumerate(src_tape)])
-    pv = arr([_dev(x, f, (N,), f"vol_n[{i}]") for i, x in enumerate(vol_n)])
-    pm = arr([_dev(x, f, (N, 3), f"mom_n[{i}]") for i, x in enumerate(mom_n)])
-    rc = lib().rt_step_adjoint_run(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), n, ps, pt, pv, pm,
+    rc = lib().rt_step_adjoint_run(mesh.ptr, ctypes.byref(params), ctypes.byref(angles.c), n, ps, pt,
                                    _dev(rho, f, (N,), "rho"), _dev(kP, f, (N,), "kP"), _dev(kJ, f, (N,), "kJ"),
                                    _dev(ks, f, (N,), "ks"), _dev(lamI, td, (N, K), "lamI"),
                                    _dev(lamE, f, (N,), "lamE"), _dev(lamM, f, (N, 3), "lamM"),

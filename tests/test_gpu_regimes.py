@@ -175,34 +175,42 @@ def test_adjoint_matches_oracle(regime, K, layout):
 
 
 def _taped_run(dp, steps):
-    """`steps` taped steps with source tapes; the per-step records and the loss seed."""
+    """`steps` taped steps, each output in a buffer of its own: per step (output, source tape,
+    I*, and the volume, momentum and gas energy before it)."""
     N = dp.I.shape[0]
     rec = []
     for _ in range(steps):
         vol_n, mom_n, etot_n = dp.vol.clone(), dp.mom.clone(), dp.etot.clone()
-        Istar = torch.empty_like(dp.I)
+        Istar, out = torch.empty_like(dp.I), torch.empty_like(dp.I)
         tape = torch.full((N, rt.SRC_TAPE), float("nan"), dtype=torch.float64, device="cuda")
-        rt.step_taped(dp.mesh, dp.params, dp.angles, dp.I, dp.I2, Istar, dp.vol, dp.rho, dp.mom, dp.etot, dp.kP,
+        rt.step_taped(dp.mesh, dp.params, dp.angles, dp.I, out, Istar, dp.vol, dp.rho, dp.mom, dp.etot, dp.kP,
                       dp.kJ, dp.ks, src_tape=tape)
-        rec.append((Istar, tape, vol_n, mom_n, etot_n))
-        dp.I, dp.I2 = dp.I2, dp.I
+        assert torch.equal(tape[:, 6], vol_n) and torch.equal(tape[:, 7:], mom_n)  # the tape's gas columns
+        rec.append((out, tape, Istar, vol_n, mom_n, etot_n))
+        dp.I = out
     return rec
 
 
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 @pytest.mark.parametrize("K,layout,steps", [(24, None, 4), (24, ADJ, 3), (80, None, 3), (80, ADJ, 4),
                                             (120, None, 4), (80, None, 1)])
-@pytest.mark.parametrize("regime", RG)
+@pytest.mark.parametrize("regime", RG + ["stiff"])
 def test_adjoint_run_matches_oracle(regime, K, layout, steps, dtype):
     """The run adjoint (source reverse of the last step, then the transpose of each step fused
     with the source reverse of the step before it, then the transpose of step 0; the source
     reverse reading the forward's taped sums and temperature) against the oracle's reverse
     mode: paired layouts (K = 24: 4 lanes x 6, K = 80: 8 x 10; antipodes K/2 apart or side by
     side) and the general one (K = 120), odd and even step counts (the chain ends in either
-    of its two buffers).  FP64 within 1e-10 of the oracle; its energy and momentum adjoints
-    within 1e-12 of the per-step adjoint's.  FP32 within 1e-5 (intensity gradient) and 1e-4
-    (opacity gradient), as the checkpointed FP32 gradient."""
-    p, _ = _order(regime_problem(regime, index=2, n=8, K=K, steps=steps), layout)
+    of its two buffers).  The source reverse reads each step's output, inverting the update
+    for Gamma^4 I*; "stiff" takes optical depths of 1e-3 to 1e3 per cell (r down to ~1e-3,
+    where that inversion cancels).  FP64 within 1e-10 of the oracle; its energy and momentum
+    adjoints within 1e-12 of the per-step adjoint's.  FP32 within 1e-5 (intensity gradient)
+    and 1e-4 (opacity gradient), as the checkpointed FP32 gradient."""
+    if regime == "stiff":
+        p = regime_problem("c", index=1, n=8, K=K, steps=steps)  # the PLM recipe's opacities, upwind steps
+    else:
+        p = regime_problem(regime, index=2, n=8, K=K, steps=steps)
+    p, _ = _order(p, layout)
     st = p.state
     dp = DeviceProblem(p, dtype=dtype, flags=rt.MESH_ADJOINT)
     rec = _taped_run(dp, steps)
@@ -211,11 +219,11 @@ def test_adjoint_run_matches_oracle(regime, K, layout, steps, dtype):
     seed = torch.zeros_like(dp.I)
     rt.flux_loss(dp.mesh, dp.params, dp.angles, dp.I, _d(u), loss, seed)
     lamI, lamE, lamM, dk = seed.clone(), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom), torch.zeros_like(dp.kP)
-    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [r[0] for r in rec], [r[1] for r in rec],
-                        [r[2] for r in rec], [r[3] for r in rec], dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM, dk, dk)
+    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [r[0] for r in rec], [r[1] for r in rec], dp.rho, dp.kP,
+                        dp.kJ, dp.ks, lamI, lamE, lamM, dk, dk)
     # the per-step adjoint on the same records
     lamI2, lamE2, lamM2, dk2 = seed.clone(), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom), torch.zeros_like(dp.kP)
-    for I_star, _, vol_n, mom_n, etot_n in reversed(rec):
+    for _, _, I_star, vol_n, mom_n, etot_n in reversed(rec):
         rt.step_adjoint(dp.mesh, dp.params, dp.angles, I_star, vol_n, dp.rho, mom_n, etot_n, dp.kP, dp.kJ, dp.ks,
                         lamI2, lamE2, lamM2, dk2, dk2)
     torch.cuda.synchronize()
@@ -237,10 +245,10 @@ def test_adjoint_run_refuses_bad_records():
     dp = DeviceProblem(p, flags=rt.MESH_ADJOINT)
     rec = _taped_run(dp, 2)
     lamI, lamE, lamM = torch.zeros_like(dp.I), torch.zeros_like(dp.etot), torch.zeros_like(dp.mom)
-    args = lambda r: ([x[0] for x in r], [x[1] for x in r], [x[2] for x in r], [x[3] for x in r])
-    # I_star of a step overlapping lamI
+    args = lambda r: ([x[0] for x in r], [x[1] for x in r])
+    # the output of a step overlapping lamI
     with pytest.raises(rt.RTError) as e:
-        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, *args(rec), dp.rho, dp.kP, dp.kJ, dp.ks, rec[1][0],
+        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, *args(rec), dp.rho, dp.kP, dp.kJ, dp.ks, rec[0][0],
                             lamE, lamM)
     assert e.value.code == rt.RT_EINVAL
     # without the adjoint buffer
@@ -251,10 +259,10 @@ def test_adjoint_run_refuses_bad_records():
     assert e.value.code == rt.RT_ESTATE
     # mismatched record lists are refused by the binding; zero steps leave the adjoints alone
     with pytest.raises(ValueError):
-        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [rec[0][0]], [], [], [], dp.rho, dp.kP, dp.kJ, dp.ks,
+        rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [rec[0][0]], [], dp.rho, dp.kP, dp.kJ, dp.ks,
                             lamI, lamE, lamM)
     lamI.fill_(2.0)
-    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [], [], [], [], dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM)
+    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, [], [], dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM)
     torch.cuda.synchronize()
     assert bool((lamI == 2.0).all())
 
