@@ -264,7 +264,6 @@ __global__ __launch_bounds__(RT_BLOCK) void k_moments16(int64_t N, int K, const 
   if (cell >= N) return;  // whole lane groups
   const int l = threadIdx.x % 4;
   const int nch = K / EPC;  // chunks per row
-  using V = typename rt_vec4<T>::type;
   // the lane's chunks, all loads issued before any is used
   const char *row = (const char *)(I + cell * (int64_t)K);
   T x[CPL][EPC];
@@ -319,6 +318,112 @@ __global__ __launch_bounds__(RT_BLOCK) void k_moments16(int64_t N, int K, const 
       if (l == c - b) o = v[c];
     if (b + l < 10) out[10 * cell + b + l] = o;
   }
+}
+
+// The same moments for an antipodal set (pair kind 1: angle k's antipode at k + K/2; 2: at
+// k + 1 for even k).  Each pair (k, k'), n_k' = -n_k and W_k' = W_k, adds W (I_k + I_k') to
+// the energy and the pressure and W (I_k - I_k') n_k to the flux: one direction read and
+// half the multiply-adds per angle.  Lane l of a cell's 4 takes chunks l, l + 4, ... of the
+// first half of the row with their antipodes' chunks (kind 1), or whole chunks holding
+// EPC / 2 pairs (kind 2).  Needs what the chunked kernel needs, and K / 2 a multiple of
+// EPC for kind 1.
+template <typename T, int CPL, int PAIRED>
+__global__ __launch_bounds__(RT_BLOCK) void k_moments16p(int64_t N, int K, const double *dirs, const double *W,
+                                                         double c_light, const T *I, double *out, int64_t nblk) {
+  constexpr int EPC = 16 / sizeof(T);          // elements per chunk
+  constexpr int PPC = PAIRED == 1 ? EPC : EPC / 2;  // pairs per chunk (kind 1: with its antipode chunk)
+  __shared__ double4 s_dw[RT_K_MAX];           // (W, n_x, n_y, n_z) per angle
+  for (int k = threadIdx.x; k < K; k += RT_BLOCK) s_dw[k] = double4{W[k], dirs[3 * k], dirs[3 * k + 1], dirs[3 * k + 2]};
+  __syncthreads();
+  const int64_t lb = rt_logical_block(nblk);
+  if (lb < 0) return;
+  const int64_t cell = lb * (RT_BLOCK / 4) + threadIdx.x / 4;
+  if (cell >= N) return;  // whole lane groups
+  const int l = threadIdx.x % 4;
+  const int nc = PAIRED == 1 ? K / (2 * EPC) : K / EPC;  // chunks the lanes walk
+  const char *row = (const char *)(I + cell * (int64_t)K);
+  T x[CPL][EPC], y[CPL][EPC];
+  auto load = [&](T(&v)[EPC], int ch) {
+    if constexpr (EPC == 4) {
+      const float4 a = *(const float4 *)(row + 16 * ch);
+      v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    } else {
+      const double2 a = *(const double2 *)(row + 16 * ch);
+      v[0] = a.x; v[1] = a.y;
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int ch = l + 4 * c;
+    if (ch < nc) {
+      load(x[c], ch);
+      if (PAIRED == 1) load(y[c], ch + nc);
+    }
+  }
+  double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int ch = l + 4 * c;
+    if (ch >= nc) continue;
+#pragma unroll
+    for (int e = 0; e < PPC; ++e) {
+      const double a = (double)(PAIRED == 1 ? x[c][e] : x[c][2 * e]);
+      const double b = (double)(PAIRED == 1 ? y[c][e] : x[c][2 * e + 1]);
+      const double4 d = s_dw[EPC * ch + (PAIRED == 1 ? e : 2 * e)];
+      const double t = d.x * (a + b), u = d.x * (a - b);
+      const double tx = t * d.y, ty = t * d.z, tz = t * d.w;
+      m[0] += t;
+      m[1] += u * d.y;
+      m[2] += u * d.z;
+      m[3] += u * d.w;
+      m[4] += tx * d.y;
+      m[5] += ty * d.z;
+      m[6] += tz * d.w;
+      m[7] += tx * d.z;
+      m[8] += tx * d.w;
+      m[9] += ty * d.w;
+    }
+  }
+  const double fourpi = 4.0 * RT_PI;
+  double v[10];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) v[c] = rt_group_sum<4>(m[c]) * (c >= 1 && c <= 3 ? fourpi * c_light : fourpi);
+  // lane l writes components l, l + 4 and (l < 2) l + 8
+#pragma unroll
+  for (int b = 0; b < 10; b += 4) {
+    double o = v[b];
+#pragma unroll
+    for (int c = b + 1; c < b + 4 && c < 10; ++c)
+      if (l == c - b) o = v[c];
+    if (b + l < 10) out[10 * cell + b + l] = o;
+  }
+}
+
+template <typename T, int CPL, int PAIRED>
+hipError_t launch_moments16p(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                             const void *I, double *out, hipStream_t s) {
+  const int64_t nblk = (m->N + RT_BLOCK / 4 - 1) / (RT_BLOCK / 4);
+  hipLaunchKernelGGL((k_moments16p<T, CPL, PAIRED>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), 0, s, m->N,
+                     K, dirs, W, c_light, (const T *)I, out, nblk);
+  return hipGetLastError();
+}
+
+template <typename T, int PAIRED>
+hipError_t dispatch_moments16p(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
+                               const void *I, double *out, hipStream_t s) {
+  constexpr int EPC = 16 / sizeof(T);
+  const int nc = PAIRED == 1 ? K / (2 * EPC) : K / EPC;
+  switch ((nc + 3) / 4) {  // chunks (kind 1: chunk pairs) per lane
+    case 1: return launch_moments16p<T, 1, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 2: return launch_moments16p<T, 2, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 3: return launch_moments16p<T, 3, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 4: return launch_moments16p<T, 4, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 5: return launch_moments16p<T, 5, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 6: return launch_moments16p<T, 6, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 7: return launch_moments16p<T, 7, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+    case 8: return launch_moments16p<T, 8, PAIRED>(m, K, dirs, W, c_light, I, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int CPL>
@@ -408,10 +513,17 @@ hipError_t diag_t(const rt_mesh *m, int K, const double *dirs, const double *W, 
 
 template <typename T>
 hipError_t moments_t(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light, const void *I,
-                     double *out, hipStream_t s) {
+                     double *out, int paired, hipStream_t s) {
   // rows of whole 16-byte chunks starting 16-byte aligned: the chunked kernel, 4 lanes per cell
   constexpr int EPC = 16 / sizeof(T);
-  if (K % EPC == 0 && ((uintptr_t)I & 15u) == 0) {
+  const bool chunked = K % EPC == 0 && ((uintptr_t)I & 15u) == 0;
+  // antipodal sets whose pairs sit whole in the chunks (kind 2) or fill whole chunks in each
+  // half of the row (kind 1): the paired form
+  if (chunked && paired == 2 && EPC % 2 == 0 && K <= 32 * EPC)
+    return dispatch_moments16p<T, 2>(m, K, dirs, W, c_light, I, out, s);
+  if (chunked && paired == 1 && K % (2 * EPC) == 0 && K <= 64 * EPC)
+    return dispatch_moments16p<T, 1>(m, K, dirs, W, c_light, I, out, s);
+  if (chunked) {
     switch ((K / EPC + 3) / 4) {  // chunks per lane
       case 1: return launch_moments16<T, 1>(m, K, dirs, W, c_light, I, out, s);
       case 2: return launch_moments16<T, 2>(m, K, dirs, W, c_light, I, out, s);
@@ -497,7 +609,7 @@ hipError_t rt_launch_flux_loss_noalloc(const rt_mesh *m, int K, const double *di
 }
 
 hipError_t rt_launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
-                             const void *I, double *out, int dtype, hipStream_t s) {
-  return dtype == RT_F32 ? moments_t<float>(m, K, dirs, W, c_light, I, out, s)
-                         : moments_t<double>(m, K, dirs, W, c_light, I, out, s);
+                             const void *I, double *out, int dtype, int paired, hipStream_t s) {
+  return dtype == RT_F32 ? moments_t<float>(m, K, dirs, W, c_light, I, out, paired, s)
+                         : moments_t<double>(m, K, dirs, W, c_light, I, out, paired, s);
 }

@@ -895,7 +895,7 @@ int rt_moments(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I
     if (i0 < o1 && o0 < i1) return fail(RT_EINVAL, "I and moments overlap");
   }
   hipError_t e = rt_launch_moments(m, a->K, a->dir, a->weight, p->c_light, I, moments, p->dtype,
-                                   (hipStream_t)stream);
+                                   rt_pair_kind(a->layout), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "moments kernel launch");
   return RT_OK;
 }

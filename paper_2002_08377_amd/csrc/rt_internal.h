@@ -248,7 +248,7 @@ hipError_t rt_launch_flux_loss_noalloc(const rt_mesh *m, int K, const double *di
                                        const void *I, const double *face_weight, double *loss, void *seed, int dtype,
                                        hipStream_t s);
 hipError_t rt_launch_moments(const rt_mesh *m, int K, const double *dirs, const double *W, double c_light,
-                             const void *I, double *out, int dtype, hipStream_t s);
+                             const void *I, double *out, int dtype, int paired, hipStream_t s);
 hipError_t rt_launch_diagnostics(const rt_mesh *m, int K, const double *dirs, const double *W, double c_red,
                                  double c_light, const void *I, const double *vol, const double *etot,
                                  const double *mom, double *out_dev, int dtype, hipStream_t s);

@@ -132,7 +132,10 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
     const double y = a.dt * a.c_red * rho;
     const double chi = kJ + ks;
     const T tg = (T)gam, tvx = (T)(vx * ic), tvy = (T)(vy * ic), tvz = (T)(vz * ic), tyc = (T)(y * chi);
-    double sQ = 0, s1 = 0, sG = 0, sI = 0;
+    // The four sums have positive terms only.  A lane adds its own angles' terms in the
+    // intensities' type (within APL rounding steps of the exact partial in FP32) and the
+    // lanes' partials meet in FP64.
+    T sQ_ = 0, s1_ = 0, sG_ = 0, sI_ = 0;
     // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
     // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S, so pass 2 keeps
     // only I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).
@@ -143,11 +146,11 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
       const T iG2 = iG * iG;
       const T G2 = G * G;
       const T r = rt_rcp(T(1) + tyc * G);
-      const double qk = ang.wt(q) * (double)iG2;
-      sQ += qk;
-      s1 += qk * (double)r;
-      sG += qk * (double)(G * r);
-      sI += qk * (double)(G2 * G2 * Ic[q] * r);
+      const T qk = (T)ang.wt(q) * iG2;
+      sQ_ += qk;
+      s1_ += qk * r;
+      sG_ += qk * (G * r);
+      sI_ += qk * (G2 * G2 * Ic[q] * r);
       Ic[q] *= r;
       Br[q] = r * iG2 * iG;
     };
@@ -158,10 +161,10 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
       pass1(q, tg * (T(1) - vn));
       if (PAIRED) pass1(q + P, tg * (T(1) + vn));
     }
-    sQ = rt_group_sum<LPC>(sQ);
-    s1 = rt_group_sum<LPC>(s1);
-    sG = rt_group_sum<LPC>(sG);
-    sI = rt_group_sum<LPC>(sI);
+    const double sQ = rt_group_sum<LPC>((double)sQ_);
+    const double s1 = rt_group_sum<LPC>((double)s1_);
+    const double sG = rt_group_sum<LPC>((double)sG_);
+    const double sI = rt_group_sum<LPC>((double)sI_);
     const double iQ = rt_rcp(sQ);
     const double S1 = s1 * iQ, SG = sG * iQ, SI = sI * iQ;
     const double Dd = S1 + y * kJ * SG;

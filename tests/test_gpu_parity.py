@@ -606,11 +606,16 @@ def test_largest_angle_sets_steps_match_oracle(dtype, K):
 
 
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
-@pytest.mark.parametrize("K", [8, 20, 24, 80, 120])
-def test_moments_match_oracle(dtype, K):
-    """Per-cell E_r, F_r, P_r (section 2.1) against the oracle on the stored intensities,
-    across the 8- and 16-lane layouts (K = 20: masked lanes); the sums are FP64 in both forms."""
+@pytest.mark.parametrize("K,order", [(8, None), (8, ADJ), (20, None), (24, None), (24, ADJ), (80, None),
+                                     (80, ADJ), (120, None), (120, ADJ)])
+def test_moments_match_oracle(dtype, K, order):
+    """Per-cell E_r, F_r, P_r (section 2.1) against the oracle on the stored intensities: the
+    antipodal sets (both orders) through the paired kernels, each pair's sum and difference
+    giving energy, pressure and flux; K = 20 (not antipodal, not whole 16-byte chunks in FP64)
+    through the lane layouts with masked lanes.  The sums are FP64 in both forms."""
     p = _masked_prob(7, 20) if K == 20 else _prob(0, n=7, K=K)
+    if order == ADJ:
+        p = inp.with_angle_order(p, inp.adjacent_pair_order(K))
     dp = DeviceProblem(p, dtype=dtype)
     N = p.mesh.n_cells
     out = torch.full((N, 10), float("nan"), dtype=torch.float64, device="cuda")
