@@ -216,7 +216,35 @@ class FluxLoss(torch.autograd.Function):
         return ctx.seed * g.to(ctx.seed.dtype), None, None
 
 
-def rt_steps(I0, kappa_a, etot0, mom0, system: RTSystem, n_steps: int, ckpt_every: int = 8):
+def record_bytes(system: RTSystem) -> int:
+    """Device bytes of one taped step's record: its output intensities and its source tape."""
+    elem = 4 if system.params.dtype == rt.F32 else 8
+    return system.mesh.n_cells * (system.angles.K * elem + rt.SRC_TAPE * 8)
+
+
+def auto_checkpoint_interval(system: RTSystem, n_steps: int, budget_bytes: int) -> int:
+    """The segment length for `n_steps` steps whose taped records fit in `budget_bytes`: all
+    steps (nothing recomputed) when they fit, else the longest segment that fits (at least 1).
+    A segment of L steps holds L records while it is reversed; the checkpoints of the other
+    segments (an intensity copy and the gas state each) are counted too."""
+    if n_steps <= 0:
+        return 1
+    rec = record_bytes(system)
+    ckpt = rec + 5 * 8 * system.mesh.n_cells
+    for L in range(n_steps, 0, -1):
+        n_ckpt = (n_steps + L - 1) // L - 1
+        if L * rec + n_ckpt * ckpt <= budget_bytes:
+            return L
+    return 1
+
+
+def rt_steps(I0, kappa_a, etot0, mom0, system: RTSystem, n_steps: int, ckpt_every: int | None = 8):
+    """S steps as one differentiable function.  ckpt_every=None picks the interval from the free
+    device memory: every step taped in the forward pass (no recompute) when the records fit in
+    half of it, else the longest segment that fits."""
+    if ckpt_every is None:
+        free, _ = torch.cuda.mem_get_info(I0.device)
+        ckpt_every = auto_checkpoint_interval(system, n_steps, free // 2)
     return RTSteps.apply(I0, kappa_a, etot0, mom0, system, n_steps, ckpt_every)
 
 

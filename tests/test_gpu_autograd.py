@@ -182,6 +182,19 @@ def test_checkpoint_interval_leaves_gradients_unchanged(dtype, fast):
                 assert torch.equal(a, b), (ckpt, overlap)
 
 
+def test_automatic_checkpoint_interval_gives_the_same_gradients():
+    """ckpt_every=None (every step taped when the records fit in half the free memory, as they
+    do here) against explicit intervals: bitwise the same loss and gradients."""
+    p = inp.make_problem(2, n=8, K=24, steps=5)
+    system, x = _system(p, rt.F32)
+    fw = _d(inp.loss_face_weights(p.mesh, np.random.default_rng(6)))
+    ref = _grads(system, x, fw, p.steps, 5)
+    got = _grads(system, x, fw, p.steps, None)
+    assert got[0] == ref[0]
+    for a, b in zip(got[1:], ref[1:]):
+        assert torch.equal(a, b)
+
+
 def test_all_input_gradients_match_directional_differences():
     p = inp.make_problem(2, n=8, K=24, steps=4)
     system, x = _system(p)
