@@ -702,6 +702,45 @@ def test_wide_face_count_variance_steps_match_oracle(K, layout, dtype, scheme):
         assert rel_err(dp.etot.cpu().numpy(), so.etot) < 1e-12
 
 
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("K,layout", [(24, None), (80, ADJ)])
+def test_run_adjoint_on_wide_face_count_mesh_matches_oracle(K, layout, dtype):
+    """The run adjoint (fused transpose and source reverse) on the split-face lattice (6 to 96
+    faces per cell, the loss plane through the split faces): taped steps reversed against the
+    oracle's reverse mode, FP64 within 1e-10, FP32 within 1e-5 / 1e-4."""
+    p, layout = _with_layout(_split_face_lattice_problem(K), layout)
+    st = p.state
+    dp = DeviceProblem(p, dtype=dtype, layout=layout, flags=rt.MESH_ADJOINT)
+    N = p.mesh.n_cells
+    outs, tapes = [], []
+    for _ in range(p.steps):
+        o = torch.empty_like(dp.I)
+        t = torch.empty((N, rt.SRC_TAPE), dtype=torch.float64, device="cuda")
+        rt.step_taped(dp.mesh, dp.params, dp.angles, dp.I, o, None, dp.vol, dp.rho, dp.mom, dp.etot, dp.kP, dp.kJ,
+                      dp.ks, src_tape=t)
+        outs.append(o)
+        tapes.append(t)
+        dp.I = o
+    u = inp.loss_face_weights(p.mesh, np.random.default_rng(11))
+    assert np.count_nonzero(u) > 0
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    lamI = torch.zeros_like(dp.I)
+    rt.flux_loss(dp.mesh, dp.params, dp.angles, dp.I, torch.as_tensor(u, device="cuda"), loss, lamI)
+    lamE, lamM, dk = torch.zeros_like(dp.etot), torch.zeros_like(dp.mom), torch.zeros_like(dp.kP)
+    rt.step_adjoint_run(dp.mesh, dp.params, dp.angles, outs, tapes, dp.rho, dp.kP, dp.kJ, dp.ks, lamI, lamE, lamM,
+                        dk, dk)
+    torch.cuda.synchronize()
+    Lo, gI, gk = orc.adjoint(dp.om, p.dirs, p.weights, p.phys, p.dt, dp.oracle_state(), st.rho, st.kP, st.ks,
+                             p.steps, u)
+    e = dict(L=abs(loss.item() - Lo) / abs(Lo), gI=rel_err(lamI.double().cpu().numpy(), gI),
+             gk=rel_err(dk.cpu().numpy(), gk))
+    print(K, layout, dtype, e)
+    if dtype == rt.F64:
+        assert e["L"] < 1e-12 and e["gI"] < 1e-10 and e["gk"] < 1e-10, e
+    else:
+        assert e["gI"] < 1e-5 and e["gk"] < 1e-4, e
+
+
 def test_mesh_too_dense_for_lds_is_refused_at_upload():
     """Sub-faces 6 x 6: 216 faces per slab cell, 16 consecutive cells beyond what a workgroup
     can stage for the PLM kernels (100 bytes per half-face in FP64): refused at upload with
