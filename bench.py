@@ -454,9 +454,41 @@ def cpu_config_timings(log):
     return out
 
 
+def gpu_steps_from_initial(prob, mesh, angles, dtype_code, steps, inv):
+    """`steps` fused steps of both forms' workload from its initial state: the intensities (put back
+    in the problem's angle order with `inv`, as float64 on the host) and the new temperatures."""
+    import torch
+    from paper_2002_08377_amd import rt
+    st, ph = prob.state, prob.phys
+    params = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, prob.dt, dtype_code, rt.UPWIND1)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    I = d(st.I).to(rt.torch_dtype(dtype_code)).contiguous()
+    I2 = torch.empty_like(I)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    rho, kP, kJ, ks = d(st.rho), d(st.kP), d(st.kJ), d(st.ks)
+    T = torch.zeros_like(vol)
+    for _ in range(steps):
+        rt.step(mesh, params, angles, I, I2, vol, rho, mom, etot, kP, kJ, ks, T)
+        I, I2 = I2, I
+    out = I.double().cpu().numpy()
+    return (out if inv is None else np.ascontiguousarray(out[:, inv])), T.cpu().numpy()
+
+
+def parity_vs_oracle(gpu, ref_I, ref_T, steps):
+    """Errors of the GPU forms against the oracle after the same `steps` steps: normwise
+    max|d| / max|ref| and element-wise max |d| / |ref|, for the intensities and the temperature."""
+    out = {"steps": steps, "reference": "FP64 oracle, same workload and initial state"}
+    for name, (I, T) in gpu.items():
+        dI, dT = np.abs(I - ref_I), np.abs(T - ref_T)
+        out[name] = {"I_norm": float(dI.max() / np.abs(ref_I).max()), "I_elem": float((dI / np.abs(ref_I)).max()),
+                     "T_norm": float(dT.max() / np.abs(ref_T).max()), "T_elem": float((dT / np.abs(ref_T)).max())}
+    return out
+
+
 def cpu_baseline(prob, steps, log, one_thread_steps=1):
     """The FP64 oracle (plain C, OpenMP) on the host cores: `steps` full steps of the same workload
-    on all its threads, then `one_thread_steps` on one thread."""
+    on all its threads, then `one_thread_steps` on one thread.  Returns the timing object and the
+    oracle's state and temperatures after the `steps` steps."""
     import oracle as orc
     st = prob.state
     om = orc.OracleMesh(prob.mesh, st.mesh_vel)
@@ -464,7 +496,7 @@ def cpu_baseline(prob, steps, log, one_thread_steps=1):
     N, K = st.I.shape
     threads = orc.num_threads()
     t0 = time.perf_counter()
-    orc.run(om, prob.dirs, prob.weights, prob.phys, prob.dt, s0, st.rho, st.kP, st.kJ, st.ks, steps)
+    so, To = orc.run(om, prob.dirs, prob.weights, prob.phys, prob.dt, s0, st.rho, st.kP, st.kJ, st.ks, steps)
     dt = time.perf_counter() - t0
     log(f"  oracle: {steps} steps in {dt:.2f} s on {threads} threads")
     out = dict(value=N * K * steps / dt, unit="cell-angle updates/s", cores=threads, kind="oracle",
@@ -482,7 +514,7 @@ def cpu_baseline(prob, steps, log, one_thread_steps=1):
         log(f"  oracle: {one_thread_steps} step(s) in {d1:.2f} s on 1 thread")
         out["one_thread"] = dict(value=N * K * one_thread_steps / d1, unit="cell-angle updates/s", cores=1,
                                  sample=f"{one_thread_steps} full step(s) of the same workload ({d1:.1f} s)")
-    return out
+    return out, so.I, To
 
 
 def main():
@@ -619,14 +651,24 @@ def main():
     }
     if not args.no_extensions:
         out["extensions"] = run_extensions(prob, mesh, angles, log)
+    gpu_short = {}
+    if args.cpu_steps > 0:
+        # both forms over the oracle's steps, for the accuracy comparison after the CPU baseline
+        for name, code in (("f32", rt.F32), ("f64", rt.F64)):
+            p_form, a_form, inv_form = setup[name]
+            gpu_short[name] = gpu_steps_from_initial(p_form, mesh, a_form, code, args.cpu_steps, inv_form)
     mesh.free()
     if not args.no_fwd_adj:
         out["fwd_adj"] = run_fwd_adj(log)
     if not args.no_plm:
         out["plm"] = run_plm(log)
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_steps, log)
+        out["cpu_baseline"], ref_I, ref_T = cpu_baseline(prob, args.cpu_steps, log)
         out["cpu_baseline"]["configs"] = cpu_config_timings(log)
+        out["parity_vs_oracle"] = parity_vs_oracle(gpu_short, ref_I, ref_T, args.cpu_steps)
+        log(f"  vs oracle after {args.cpu_steps} steps: " + ", ".join(
+            f"{k} I {v['I_norm']:.2e} (elem {v['I_elem']:.2e}) T {v['T_norm']:.2e}"
+            for k, v in out["parity_vs_oracle"].items() if isinstance(v, dict)))
     print(json.dumps(out), flush=True)
 
 
