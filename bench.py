@@ -191,10 +191,12 @@ def run_plm(log):
     p0 = inp.make_problem(1)
     N, K = p0.state.I.shape
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
-    # each form in its faster angle order, as in the step measurement
-    orders = {"f64": inp.with_angle_order(p0, inp.adjacent_pair_order(K)), "f32": p0}
+    # both forms with each antipode stored beside its angle (their faster order), as in the step
+    # measurement
+    p_adj = inp.with_angle_order(p0, inp.adjacent_pair_order(K))
+    orders = {"f64": p_adj, "f32": p_adj}
     out = {"workload": f"plm_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p0.steps,
-           "scheme": "plm_vl2", "angle_order": {"f64": "antipodes adjacent", "f32": "antipode at k + K/2"}}
+           "scheme": "plm_vl2", "angle_order": "antipodes adjacent"}
     for still in (False, True):
         w = np.zeros_like(p0.state.mesh_vel) if still else p0.state.mesh_vel
         mesh = rt.Mesh.from_inputs(p0.mesh, w, k_max=K, flags=rt.MESH_PLM)

@@ -16,7 +16,10 @@ namespace {
 // its records (the two estimator vectors, the extrapolation offset and the neighbour)
 // are staged in LDS once and every lane group reads them from there.  Neighbour rows
 // are gathered two faces per batch, all loads of a batch issued before any is used.
-template <typename T, int LPC, int APL>
+// Output: the limited gradient as [N][3][K] (PACKED false), or, for the PLM step's own
+// stage 2, each cell and angle's (phi, alpha grad phi) as one 4-vector, [N][K][4]
+// (PACKED true), so stage 2 gathers a neighbour's face state with one access per angle.
+template <typename T, int LPC, int APL, bool PACKED>
 __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ hf_nbr, const void *hf_gp,
                                                        const void *hf_rel, const double *__restrict__ vol0,
@@ -119,13 +122,18 @@ __global__ __launch_bounds__(RT_BLOCK) void k_gradient(int64_t N, int K, const i
     if (dmax[q] > T(0)) al = fmin(al, (hi[q] - s[q]) * rt_rcp_refined(dmax[q]));
     if (dmin[q] < T(0)) al = fmin(al, (lo[q] - s[q]) * rt_rcp_refined(dmin[q]));
     const int k = kk[q];
-    G[(cell * 3 + 0) * K + k] = al * gx[q];
-    G[(cell * 3 + 1) * K + k] = al * gy[q];
-    G[(cell * 3 + 2) * K + k] = al * gz[q];
+    if constexpr (PACKED) {
+      using V4 = typename rt_vec4<T>::type;
+      ((V4 *)G)[cell * K + k] = V4{s[q], al * gx[q], al * gy[q], al * gz[q]};
+    } else {
+      G[(cell * 3 + 0) * K + k] = al * gx[q];
+      G[(cell * 3 + 1) * K + k] = al * gy[q];
+      G[(cell * 3 + 2) * K + k] = al * gz[q];
+    }
   }
 }
 
-template <typename T, int LPC, int APL>
+template <typename T, int LPC, int APL, bool PACKED>
 hipError_t launch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
   using V4 = typename rt_vec4<T>::type;
   const int64_t cpb = RT_BLOCK / LPC;
@@ -135,45 +143,47 @@ hipError_t launch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s
   const int cap = cpb == 16 ? m->hf_cap16 : m->hf_cap32;
   const size_t smem = (3 * sizeof(V4) + sizeof(int32_t)) * (size_t)cap;
   if (smem > (size_t)m->lds_max) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_gradient<T, LPC, APL>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s, m->N,
+  hipLaunchKernelGGL((k_gradient<T, LPC, APL, PACKED>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s, m->N,
                      K, m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, cap, nblk);
   return hipGetLastError();
 }
 
-template <typename T> hipError_t dispatch16(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+template <typename T, bool PACKED> hipError_t dispatch16(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
   switch ((K + 15) / 16) {
-    case 1: return launch<T, 16, 1>(m, K, I, G, s);
-    case 2: return launch<T, 16, 2>(m, K, I, G, s);
-    case 3: return launch<T, 16, 3>(m, K, I, G, s);
-    case 4: return launch<T, 16, 4>(m, K, I, G, s);
-    case 5: return launch<T, 16, 5>(m, K, I, G, s);
-    case 6: return launch<T, 16, 6>(m, K, I, G, s);
-    case 7: return launch<T, 16, 7>(m, K, I, G, s);
-    case 8: return launch<T, 16, 8>(m, K, I, G, s);
+    case 1: return launch<T, 16, 1, PACKED>(m, K, I, G, s);
+    case 2: return launch<T, 16, 2, PACKED>(m, K, I, G, s);
+    case 3: return launch<T, 16, 3, PACKED>(m, K, I, G, s);
+    case 4: return launch<T, 16, 4, PACKED>(m, K, I, G, s);
+    case 5: return launch<T, 16, 5, PACKED>(m, K, I, G, s);
+    case 6: return launch<T, 16, 6, PACKED>(m, K, I, G, s);
+    case 7: return launch<T, 16, 7, PACKED>(m, K, I, G, s);
+    case 8: return launch<T, 16, 8, PACKED>(m, K, I, G, s);
   }
   return hipErrorInvalidValue;
 }
 
 // Small angle sets take 8 lanes per cell (32-cell workgroups); if their half-face
 // records do not fit in LDS, 16 lanes (16-cell workgroups) halve the staging.
-template <typename T> hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
-  if (K % 16 == 0 || K > 64) return dispatch16<T>(m, K, I, G, s);
+template <typename T, bool PACKED> hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+  if (K % 16 == 0 || K > 64) return dispatch16<T, PACKED>(m, K, I, G, s);
   hipError_t e = hipErrorInvalidValue;
   switch ((K + 7) / 8) {
-    case 1: e = launch<T, 8, 1>(m, K, I, G, s); break;
-    case 2: e = launch<T, 8, 2>(m, K, I, G, s); break;
-    case 3: e = launch<T, 8, 3>(m, K, I, G, s); break;
-    case 4: e = launch<T, 8, 4>(m, K, I, G, s); break;
-    case 5: e = launch<T, 8, 5>(m, K, I, G, s); break;
-    case 6: e = launch<T, 8, 6>(m, K, I, G, s); break;
-    case 7: e = launch<T, 8, 7>(m, K, I, G, s); break;
-    case 8: e = launch<T, 8, 8>(m, K, I, G, s); break;
+    case 1: e = launch<T, 8, 1, PACKED>(m, K, I, G, s); break;
+    case 2: e = launch<T, 8, 2, PACKED>(m, K, I, G, s); break;
+    case 3: e = launch<T, 8, 3, PACKED>(m, K, I, G, s); break;
+    case 4: e = launch<T, 8, 4, PACKED>(m, K, I, G, s); break;
+    case 5: e = launch<T, 8, 5, PACKED>(m, K, I, G, s); break;
+    case 6: e = launch<T, 8, 6, PACKED>(m, K, I, G, s); break;
+    case 7: e = launch<T, 8, 7, PACKED>(m, K, I, G, s); break;
+    case 8: e = launch<T, 8, 8, PACKED>(m, K, I, G, s); break;
   }
-  return e == hipErrorInvalidConfiguration ? dispatch16<T>(m, K, I, G, s) : e;
+  return e == hipErrorInvalidConfiguration ? dispatch16<T, PACKED>(m, K, I, G, s) : e;
 }
 
 }  // namespace
 
-hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, hipStream_t s) {
-  return dtype == RT_F32 ? dispatch<float>(m, K, I, grad, s) : dispatch<double>(m, K, I, grad, s);
+hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, bool packed,
+                              hipStream_t s) {
+  if (packed) return dtype == RT_F32 ? dispatch<float, true>(m, K, I, grad, s) : dispatch<double, true>(m, K, I, grad, s);
+  return dtype == RT_F32 ? dispatch<float, false>(m, K, I, grad, s) : dispatch<double, false>(m, K, I, grad, s);
 }

@@ -182,7 +182,8 @@ int run_step(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *I_i
   s1.write_gas = 0;
   hipError_t e = rt_launch_step(s1, p->dtype, st);
   if (e != hipSuccess) return hip_fail(e, "stage-1 kernel launch");
-  e = rt_launch_gradient(m, a->K, m->I_half, m->grad, p->dtype, st);
+  // FP32: (I_half, gradient) packed per cell and angle for stage 2; FP64: the gradient alone
+  e = rt_launch_gradient(m, a->K, m->I_half, m->grad, p->dtype, p->dtype == RT_F32, st);
   if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
   // stage 2: reconstructed fluxes of the half-step state on the start-of-step charges, source on gas^n
   rt_step_args s2 = s;
@@ -353,7 +354,7 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
     RT_ALLOC(m->hf_gp32, sizeof(float4) * 2 * H);
     RT_ALLOC(m->hf_rel32, sizeof(float4) * 2 * H);
     RT_ALLOC(m->I_half, sizeof(double) * N * k_max);
-    RT_ALLOC(m->grad, sizeof(double) * 3 * N * k_max);
+    RT_ALLOC(m->grad, sizeof(double) * 4 * N * k_max);
   }
   if (flags & RT_MESH_ADJOINT) RT_ALLOC(m->lam_star, sizeof(double) * N * k_max);
   RT_ALLOC(m->red, sizeof(double) * RT_NDIAG * nred);
@@ -511,7 +512,7 @@ int rt_gradient(rt_mesh *m, const rt_params *p, const rt_angles *a, const void *
   if (rc) return rc;
   if ((rc = check_ptrs({I, grad}))) return rc;
   if (!(m->flags & RT_MESH_PLM)) return fail(RT_ESTATE, "rt_gradient needs a mesh uploaded with RT_MESH_PLM");
-  hipError_t e = rt_launch_gradient(m, a->K, I, grad, p->dtype, (hipStream_t)stream);
+  hipError_t e = rt_launch_gradient(m, a->K, I, grad, p->dtype, false, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
   return RT_OK;
 }

@@ -30,7 +30,8 @@ struct rt_mesh {
   float4 *hf_rel32;
   // scratch
   void *I_half;       // [N][k_max] doubles (RT_MESH_PLM), used in either precision
-  void *grad;         // [N][3][k_max] doubles (RT_MESH_PLM)
+  void *grad;         // RT_MESH_PLM, 4 N k_max doubles: FP32 (I_half, limited gradient) per cell
+                     // and angle [N][K][4]; FP64 the limited gradient [N][3][K]
   void *lam_star;     // [N][k_max] doubles (RT_MESH_ADJOINT)
   double *red;        // reduction partials, RT_NDIAG * n_red_blocks doubles
   double *red_mid;    // first fold of the partials, RT_NDIAG * RT_BLOCK doubles
@@ -61,7 +62,7 @@ struct rt_step_args {
   const double *W;
   const void *I_in;    // intensities read by transport (start-of-step charges)
   const void *I_half;  // PLM stage 2: half-step intensities (face states)
-  const void *grad;    // PLM stage 2: limited gradients of I_half
+  const void *grad;    // PLM stage 2: FP32 (I_half, limited gradient) [N][K][4]; FP64 gradient [N][3][K]
   void *I_out;
   void *I_star_out;    // upwind with source: when set, the transported intensities (the
                        // source's input) are stored here as well
@@ -139,7 +140,8 @@ static inline int rt_step_lanes(int K, int paired) {
 }
 
 hipError_t rt_launch_step(const rt_step_args &a, int dtype, hipStream_t s);
-hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, hipStream_t s);
+hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, bool packed,
+                              hipStream_t s);
 
 struct rt_adj_args {
   int64_t N;
