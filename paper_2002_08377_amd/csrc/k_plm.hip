@@ -143,12 +143,13 @@ hipError_t launch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s
   const int cap = cpb == 16 ? m->hf_cap16 : m->hf_cap32;
   const size_t smem = (3 * sizeof(V4) + sizeof(int32_t)) * (size_t)cap;
   if (smem > (size_t)m->lds_max) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_gradient<T, LPC, APL, PACKED>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s, m->N,
-                     K, m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, cap, nblk);
+  hipLaunchKernelGGL((k_gradient<T, LPC, APL, PACKED>), dim3((unsigned)rt_grid_for(nblk)), dim3(RT_BLOCK), smem, s,
+                     m->N, K, m->row_ptr, m->hf_nbr, gp, rel, m->vol0, (const T *)I, (T *)G, cap, nblk);
   return hipGetLastError();
 }
 
-template <typename T, bool PACKED> hipError_t dispatch16(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+template <typename T, bool PACKED>
+hipError_t dispatch16(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
   switch ((K + 15) / 16) {
     case 1: return launch<T, 16, 1, PACKED>(m, K, I, G, s);
     case 2: return launch<T, 16, 2, PACKED>(m, K, I, G, s);
@@ -164,7 +165,8 @@ template <typename T, bool PACKED> hipError_t dispatch16(const rt_mesh *m, int K
 
 // Small angle sets take 8 lanes per cell (32-cell workgroups); if their half-face
 // records do not fit in LDS, 16 lanes (16-cell workgroups) halve the staging.
-template <typename T, bool PACKED> hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
+template <typename T, bool PACKED>
+hipError_t dispatch(const rt_mesh *m, int K, const void *I, void *G, hipStream_t s) {
   if (K % 16 == 0 || K > 64) return dispatch16<T, PACKED>(m, K, I, G, s);
   hipError_t e = hipErrorInvalidValue;
   switch ((K + 7) / 8) {
@@ -184,6 +186,7 @@ template <typename T, bool PACKED> hipError_t dispatch(const rt_mesh *m, int K, 
 
 hipError_t rt_launch_gradient(const rt_mesh *m, int K, const void *I, void *grad, int dtype, bool packed,
                               hipStream_t s) {
-  if (packed) return dtype == RT_F32 ? dispatch<float, true>(m, K, I, grad, s) : dispatch<double, true>(m, K, I, grad, s);
+  if (packed)
+    return dtype == RT_F32 ? dispatch<float, true>(m, K, I, grad, s) : dispatch<double, true>(m, K, I, grad, s);
   return dtype == RT_F32 ? dispatch<float, false>(m, K, I, grad, s) : dispatch<double, false>(m, K, I, grad, s);
 }
