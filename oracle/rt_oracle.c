@@ -885,11 +885,15 @@ void or_source_mg(int64_t N, int K, int G, const double *dirs, const double *W, 
  * (r_k = 1/(1 + y chi Gamma_k)); f' follows from dS/dchi = -y sum W~ Gamma r^2 (.)
  * and dk/dT = b k / T.  f is negative as T -> 0 and grows like rho cv T, but it
  * need not be monotone, so plain Newton can fail (READING: the paper names the
- * method, not its safeguards).  The root is first bracketed from T^n (doubling
- * upward while f < 0, halving downward while f > 0), then Newton steps are taken
- * inside the bracket, a bisection replacing any larger step that leaves it, until
- * a step changes T by at most 1e-14 T; that converged step is taken as it is, even
- * when rounding puts it on the bracket's end (at most 200 evaluations in all).  The comoving
+ * method, not its safeguards).  The far end of a bracket is found from T^n (doubling
+ * upward while f < 0, halving downward while f > 0); Newton steps then start at T^n,
+ * which becomes the bracket's near end at the first step, so the bracket is [T^n, hi]
+ * (or [lo, T^n]), and a bisection replaces any larger step that leaves it, until a
+ * step changes T by at most 1e-14 T; that converged step is taken as it is, even when
+ * rounding puts it on the bracket's end (at most 200 evaluations in all).  Where f has
+ * several roots the iteration is meant to give the first one met from T^n in the
+ * direction of f's sign (the smallest above T^n, or the largest below it); the tests
+ * check that by a scan of f written apart from this code.  The comoving
  * sums are then evaluated at the final T, and the per-angle update and the
  * bookkeeping are those of the grey update with the opacities at T^{n+1}.
  */

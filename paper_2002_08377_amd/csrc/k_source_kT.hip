@@ -5,11 +5,14 @@
 //   f(T) = rho cv (T - T^n) + dt c rho [kP a T^4 S1 - 4 pi kJ SI] / D,
 // whose comoving sums depend on T through chi = kJ(T) + ks; every evaluation sums the
 // angles again (S1, SG, SI and their chi-derivatives) and reduces over the lanes, so
-// all lanes of a cell take the same steps.  The root is bracketed from T^n (doubling
-// upward while f < 0, halving downward while f > 0), then found by Newton steps kept
-// inside the bracket (bisection when a step leaves it) until a step changes T by at most
-// 1e-14 T (such a step is taken as it is); at most 200 evaluations, about 5 in practice.  Per-angle arithmetic is FP64 in both precision
-// forms; the update and the bookkeeping are those of the grey source.
+// all lanes of a cell take the same steps.  The bracket's far end is found from T^n
+// (doubling upward while f < 0, halving downward while f > 0); Newton steps start at T^n,
+// the bracket's near end from the first step on, and are kept inside [T^n, hi] (or
+// [lo, T^n]; bisection when a step leaves it) until a step changes T by at most 1e-14 T
+// (such a step is taken as it is); at most 200 evaluations, about 5 in practice.  Where f
+// has several roots this gives the first met from T^n in the direction of f's sign.
+// Per-angle arithmetic is FP64 in both precision forms; the update and the bookkeeping
+// are those of the grey source.
 #include "rt_step_common.h"
 
 namespace {

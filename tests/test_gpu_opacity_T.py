@@ -3,12 +3,15 @@ GPU against the oracle, which runs the same bracketed, safeguarded Newton: FP64
 <= 1e-12 on intensities, temperature and gas; FP32 form <= 1e-6 on intensities,
 temperature and gas energy (its gas is booked from the FP32-rounded intensities,
 so it differs from the FP64 oracle at FP32 rounding) and over 3 steps <= 1e-5, for
-constant, rising, falling (Kramers-like) and mixed power laws; 3-step runs;
-invalid laws and the PLM scheme are refused."""
+constant, rising, falling (Kramers-like) and mixed power laws; 3-step runs; steep
+laws with several temperature roots take the first root met from T^n (checked against
+an independent scan of the temperature equation); invalid laws and the PLM scheme are
+refused."""
 import numpy as np
 import pytest
 import torch
 
+import kt_roots as kt
 import oracle as orc
 from gpu_helpers import rel_err
 from paper_2002_08377_amd import inputs as inp
@@ -78,6 +81,56 @@ def test_source_kT_extreme_laws_match_oracle(b, Tr):
     assert rel_err(T.cpu().numpy(), To) < 1e-12
     assert rel_err(etot.cpu().numpy(), eo) < 1e-12
     mesh.free()
+
+
+@pytest.mark.parametrize("law", range(len(kt.STEEP_LAWS)))
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_source_kT_steep_laws_take_the_first_root(dtype, law):
+    """Steep laws where a share of the cells have several temperature roots: the kernel's
+    temperature is the first root met from T^n in the direction of f's sign, found by a
+    dense scan of f written apart from both the kernel and the oracle (tests/kt_roots.py),
+    and agrees with the oracle.  Temperatures are compared within the rounding of f's terms
+    over |f'| at the root (eps 1e-11: the kernel's power law exp(b ln(T/T_ref)) is within
+    (|b ln| + 2) ulp, |b ln| < 100 here); intensities and gas energy within 1e-9 in FP64
+    (their logarithmic sensitivity to T is at most 4 + |bP| + |bJ| < 25, times relative
+    root errors up to ~2e-11 where the root is ill-conditioned), 1e-6 in the FP32 form."""
+    bP, bJ, dt, scale = kt.STEEP_LAWS[law]
+    K = 24
+    p = inp.make_problem(0, n=7, K=K, steps=1)
+    N = p.mesh.n_cells
+    ph = inp.Physics(c_red=30.0, c_light=100.0)
+    rng = np.random.default_rng(300 + law)
+    d, w, rho, mom0, etot0, I0, kP0, kJ0, ks = kt.steep_cells(N, K, rng, scale, lambda k: (p.dirs, p.weights),
+                                                                ph.cv)
+    mesh = rt.Mesh.from_inputs(p.mesh, p.state.mesh_vel, k_max=K)
+    ang = rt.AngleSet(d, w)
+    prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, dt, dtype)
+    td = rt.torch_dtype(dtype)
+    I = _d(I0).to(td)
+    mom, etot = _d(mom0), _d(etot0)
+    T = torch.zeros(N, dtype=torch.float64, device="cuda")
+    Tr = 1.3
+    rt.source_implicit_kT(mesh, prm, ang, I, _d(rho), mom, etot, _d(kP0), _d(kJ0), _d(ks), Tr, bP, bJ, T)
+    torch.cuda.synchronize()
+    I_in = _d(I0).to(td).double().cpu().numpy()
+    Io, mo, eo, To = orc.source_kT(d, w, ph, dt, I_in, rho, mom0, etot0, kP0, kJ0, ks, Tr, bP, bJ)
+    Tg = T.cpu().numpy()
+    several = 0
+    for i in range(N):
+        args = (d, w, ph, dt, I_in[i], rho[i], mom0[i], etot0[i], kP0[i], kJ0[i], ks[i], Tr, bP, bJ)
+        Tn = kt.cell_terms(d, w, ph, dt, I_in[i], rho[i], mom0[i], etot0[i])[3]
+        rs = kt.roots(args, Tn)
+        r = kt.first_root(args, Tn, rs)
+        several += len(rs) > 1
+        bound = kt.root_error_bound(args, r, eps=1e-11)
+        assert abs(Tg[i] - r) <= bound, (i, Tg[i], r, rs)
+        assert abs(Tg[i] - To[i]) <= bound, (i, Tg[i], To[i])
+    assert several >= N // 20
+    tol = 1e-9 if dtype == rt.F64 else 1e-6
+    assert rel_err(I.double().cpu().numpy(), Io) < tol
+    assert rel_err(etot.cpu().numpy(), eo) < tol
+    mesh.free()
+    ang.free()
 
 
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])

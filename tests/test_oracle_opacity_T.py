@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 from scipy.optimize import root
 
+import kt_roots as kt
 import oracle as orc
 from paper_2002_08377_amd import inputs as inp
 
@@ -148,3 +149,38 @@ def test_equilibrium_at_rest_is_fixed_point():
     I1, m1, e1, T1 = orc.source_kT(d, w, phys, 0.05, I, rho, mom, etot, kP0, kJ0, ks, Tr, bP, bJ)
     np.testing.assert_allclose(T1, T, rtol=1e-13)
     np.testing.assert_allclose(I1, I, rtol=1e-12)
+
+
+
+def test_steep_laws_take_the_first_root_from_Tn():
+    """Which root, where there are several.  The temperature equation f(T) = 0 is written
+    again with the angles eliminated in closed form (tests/kt_roots.py, which shares no code
+    with the oracle); a dense scan finds all its roots within a factor 1024 of T^n.  For
+    these steep laws a share of the cells have several roots, and in some of them several
+    lie inside the Newton phase's bracket [T^n, hi] (or [lo, T^n]), so the bracket alone
+    does not decide.  The oracle must return the first root met from T^n in the direction
+    of f's sign, to within the rounding of f's terms over |f'|: a Newton iteration started
+    elsewhere (at the far bracket end, or cold), a bracket searched the wrong way, or a
+    step that jumps over the first root fails this."""
+    phys = inp.Physics(c_red=30.0, c_light=100.0)
+    N, K, Tr = 100, 8, 1.3
+    crowded = 0
+    for law, (bP, bJ, dt, scale) in enumerate(kt.STEEP_LAWS):
+        rng = np.random.default_rng(100 + law)
+        d, w, rho, mom, etot, I, kP0, kJ0, ks = kt.steep_cells(N, K, rng, scale, inp.angle_set, phys.cv)
+        I1, m1, e1, T1 = orc.source_kT(d, w, phys, dt, I, rho, mom, etot, kP0, kJ0, ks, Tr, bP, bJ)
+        several = 0
+        for i in range(N):
+            args = (d, w, phys, dt, I[i], rho[i], mom[i], etot[i], kP0[i], kJ0[i], ks[i], Tr, bP, bJ)
+            Tn = kt.cell_terms(d, w, phys, dt, I[i], rho[i], mom[i], etot[i])[3]
+            rs = kt.roots(args, Tn)
+            r = kt.first_root(args, Tn, rs)
+            assert r is not None, (law, i, Tn, rs)
+            lo, hi = kt.bracket(args, Tn)
+            inside = [q for q in rs if (Tn <= q <= hi if r > Tn else lo <= q <= Tn)]
+            several += len(rs) > 1
+            crowded += len(inside) > 1
+            assert abs(T1[i] - r) <= kt.root_error_bound(args, r), (law, i, T1[i], rs)
+        # the laws are steep enough that the choice matters in a share of the cells
+        assert several >= N // 10, (law, several)
+    assert crowded >= 3
