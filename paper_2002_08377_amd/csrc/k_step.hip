@@ -225,12 +225,22 @@ k_step(rt_step_args a, int64_t nblk) {
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
           const T ax = sc * r[u].x, ay = sc * r[u].y, az = sc * r[u].z, nb = -(sd * r[u].w);
-#pragma unroll
-          for (int q = 0; q < APL; ++q) {
-            const T g = fma(az, ang.dz(q), fma(ay, ang.dy(q), fma(ax, ang.dx(q), nb)));
+          const T m2b = nb + nb;
+          // the charge through the face at the reconstructed state of its upwind side
+          auto face = [&](int q, T g) {
             const T fs = hs[q] + gsx[q] * r0[u].x + gsy[q] * r0[u].y + gsz[q] * r0[u].z;
             const T fn = xh[u][q] + xg0[u][q] * r0[u].w + xg1[u][q] * r1[u].x + xg2[u][q] * r1[u].y;
             acc[q] -= g * (g > T(0) ? fs : fn);
+          };
+          // FP32: the antipode's speed as in the upwind loop (64^3 x 80 PLM step 0.778 ->
+          // 0.760 ms); FP64 keeps three multiply-adds per angle (paired: 1.474 -> 1.489 ms)
+          constexpr bool PAIR_G = PAIRED && sizeof(T) == 4;
+          constexpr int NG = PAIR_G ? P : APL;
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            const T g = fma(az, ang.dz(q), fma(ay, ang.dy(q), fma(ax, ang.dx(q), nb)));
+            face(q, g);
+            if (PAIR_G) face(q + P, m2b - g);
           }
         }
       }

@@ -47,9 +47,10 @@ template <typename P> hipError_t dmalloc(P **p, size_t bytes) {
 }
 
 void free_mesh_arrays(rt_mesh *m) {
-  void *ptrs[] = {m->vol0,    m->D,       m->wn,       m->row_ptr, m->hf_nbr, m->hf_face, m->hf_an64,
-                  m->hf_an32, m->hf_gp64, m->hf_rel64, m->hf_gp32, m->hf_rel32, m->I_half, m->grad,
-                  m->lam_star, m->red, m->red_mid, m->wg_order16, m->wg_order32, m->wg_order64};
+  void *ptrs[] = {m->vol0,     m->D,       m->wn,      m->row_ptr,    m->hf_nbr,     m->hf_face,
+                  m->hf_an64,   m->hf_an32, m->hf_gp64, m->hf_rel64,   m->hf_gp32,    m->hf_rel32,
+                  m->gb64,      m->gb32,    m->I_half,  m->grad,       m->lam_star,   m->red,
+                  m->red_mid,   m->wg_order16, m->wg_order32, m->wg_order64};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -349,10 +350,12 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   RT_ALLOC(m->hf_an64, sizeof(double4) * H);
   RT_ALLOC(m->hf_an32, sizeof(float4) * H);
   if (plm) {
-    RT_ALLOC(m->hf_gp64, sizeof(double4) * 2 * H);
+    RT_ALLOC(m->hf_gp64, sizeof(double4) * H);
     RT_ALLOC(m->hf_rel64, sizeof(double4) * 2 * H);
-    RT_ALLOC(m->hf_gp32, sizeof(float4) * 2 * H);
+    RT_ALLOC(m->hf_gp32, sizeof(float4) * H);
     RT_ALLOC(m->hf_rel32, sizeof(float4) * 2 * H);
+    RT_ALLOC(m->gb64, sizeof(double4) * N);
+    RT_ALLOC(m->gb32, sizeof(float4) * N);
     RT_ALLOC(m->I_half, sizeof(double) * N * k_max);
     RT_ALLOC(m->grad, sizeof(double) * 4 * N * k_max);
   }
@@ -405,6 +408,7 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
   H2D(d_shift, face_shift, 3 * F);
   if (e == hipSuccess) e = rt_launch_face_speed(d_gen, d_w, d_fc, d_shift, d_nrm, d_cen, box, F, m->wn, st);
   if (e == hipSuccess) e = rt_launch_half_faces(m, d_fc, d_area, d_nrm, d_cen, d_gen, d_com, d_shift, st);
+  if (e == hipSuccess && plm) e = rt_launch_gradient_base(m, d_fc, d_area, d_cen, d_gen, d_shift, st);
   if (e == hipSuccess) e = rt_launch_volume_rate(m, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   cleanup_tmp();

@@ -24,10 +24,12 @@ struct rt_mesh {
   double4 *hf_an64;   // [H] (A n_out, A (w~.n)_out), FP64
   float4 *hf_an32;    // [H] same, FP32
   // reconstruction geometry (RT_MESH_PLM): per half-face, from the owning cell's side
-  double4 *hf_gp64;   // [H][2]: (A c/d, A/2 n_out.x), (A/2 n_out.y, A/2 n_out.z, -, -)
+  double4 *hf_gp64;   // [H]: (A c/d + A/2 n_g, 0), the neighbour's weight in the gradient
   double4 *hf_rel64;  // [H][2]: (r~ - s_self, r~ - s_nbr.x), (r~ - s_nbr.y, .z, -, -)
   float4 *hf_gp32;
   float4 *hf_rel32;
+  double4 *gb64;      // [N]: (sum over the cell's faces of A/2 n_g - A c/d, 0), its own weight
+  float4 *gb32;
   // scratch
   void *I_half;       // [N][k_max] doubles (RT_MESH_PLM), used in either precision
   void *grad;         // RT_MESH_PLM, 4 N k_max doubles: FP32 (I_half, limited gradient) per cell
@@ -112,6 +114,9 @@ hipError_t rt_launch_face_speed(const double *gen, const double *mesh_vel, const
 hipError_t rt_launch_half_faces(rt_mesh *m, const int32_t *face_cells, const double *face_area,
                                 const double *face_normal, const double *face_centroid, const double *gen,
                                 const double *com, const int8_t *face_shift, hipStream_t s);
+hipError_t rt_launch_gradient_base(rt_mesh *m, const int32_t *face_cells, const double *face_area,
+                                   const double *face_centroid, const double *gen, const int8_t *face_shift,
+                                   hipStream_t s);
 hipError_t rt_launch_volume_rate(rt_mesh *m, hipStream_t s);
 
 // Lane layout of the step kernel for K angles: (lanes per cell << 8) | angles per lane.
