@@ -47,6 +47,19 @@ def algorithmic_bytes(N, F, K, dtype):
     return N * K * 2 * sI + F * (8 + 4 * sg) + (N + 1) * 4 + 2 * F * 4 + 120 * N
 
 
+def plm_algorithmic_bytes(N, F, K, dtype):
+    """Bytes one PLM-VL2 step must move at minimum: stage 1 is a first-order step; the gradient
+    reads the half-step intensities and writes three components per cell-angle, with each face's
+    cell pair and two 3-vectors of estimator weights; stage 2 is a first-order step that also
+    reads the half-step intensities and the gradient, with each face's two extrapolation offsets."""
+    sI = 4 if dtype == "f32" else 8
+    sg = 4 if dtype == "f32" else 8
+    first = algorithmic_bytes(N, F, K, dtype)
+    gradient = N * K * 4 * sI + F * (8 + 6 * sg)
+    stage2 = first + N * K * 4 * sI + F * 6 * sg
+    return first + gradient + stage2
+
+
 def algorithmic_ops(N, F, K):
     return N * K * SOURCE_OPS_PER_CA + F * K * FACE_OPS_PER_FA
 
@@ -190,6 +203,7 @@ def run_plm(log):
     from paper_2002_08377_amd import rt
     p0 = inp.make_problem(1)
     N, K = p0.state.I.shape
+    F = p0.mesh.n_faces
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
     # both forms with each antipode stored beside its angle (their faster order), as in the step
     # measurement
@@ -223,8 +237,9 @@ def run_plm(log):
                 e0, e1 = d0[0] + d0[1], d1[0] + d1[1]
                 out.setdefault("energy_drift_still_mesh", {})[name] = abs(e1 - e0) / e0
             else:
-                out[name] = {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s",
-                             "ms_per_step": dt * 1e3 / p.steps}
+                ms = dt * 1e3 / p.steps
+                out[name] = {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s", "ms_per_step": ms,
+                             "roofline": _roofline(ms, plm_algorithmic_bytes(N, F, K, name))}
                 log(f"  plm {name}: {dt * 1e3 / p.steps:.3f} ms/step")
         mesh.free()
     log(f"  plm energy drift over {p.steps} steps (still mesh): {out['energy_drift_still_mesh']}")
