@@ -141,7 +141,8 @@ def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
     FP32 transport, checkpoints every 8 steps): cell-angle updates per second of the forward steps,
     the time covering the forward pass, the recompute and the adjoint of all steps.  Beside it the
     same pass with every step taped during the forward pass (no checkpoints, no recompute), which
-    holds all 40 steps' records at once."""
+    holds all 40 steps' records at once, and the FP64 form's checkpointed pass, whose loss and
+    gradients the FP32 form's are compared with (normwise: max |difference| / max |FP64|)."""
     import torch
     from paper_2002_08377_amd import autograd as ag
     from paper_2002_08377_amd import inputs as inp
@@ -157,39 +158,53 @@ def run_fwd_adj(log, warmup=1, reps=2, ckpt=8):
         f"{time.perf_counter() - t0:.1f} s")
     mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_ADJOINT)
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
-    system = ag.RTSystem(mesh, rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, rt.F32),
-                         rt.AngleSet(p.dirs, p.weights), d(st.rho), d(st.ks), d(st.vol))
+    angles = rt.AngleSet(p.dirs, p.weights)
+    systems = {code: ag.RTSystem(mesh, rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, code), angles,
+                                 d(st.rho), d(st.ks), d(st.vol)) for code in (rt.F32, rt.F64)}
     fw = d(inp.loss_face_weights(p.mesh, p.seeds["omega"]))
-    I0, kap, etot, mom = d(st.I).float(), d(st.kP), d(st.etot), d(st.mom)
+    kap, etot, mom = d(st.kP), d(st.etot), d(st.mom)
+    I0 = {rt.F32: d(st.I).float(), rt.F64: d(st.I)}
 
-    def once(every):
-        x = [t.clone().requires_grad_() for t in (I0, kap, etot, mom)]
+    def once(every, code):
+        x = [t.clone().requires_grad_() for t in (I0[code], kap, etot, mom)]
+        system = systems[code]
         IS = ag.rt_steps(*x, system, p.steps, every)[0]
-        ag.flux_loss(IS, fw, system).backward()
-        return x[1].grad
+        L = ag.flux_loss(IS, fw, system)
+        L.backward()
+        return float(L.detach()), x[0].grad, x[1].grad
 
-    def timed(every):
+    def timed(every, code):
         for _ in range(warmup):
-            once(every)
+            once(every, code)
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         t0 = time.perf_counter()
         for _ in range(reps):
-            g = once(every)
+            res = once(every, code)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps, bool(torch.isfinite(g).all()), torch.cuda.max_memory_allocated()
+        return (time.perf_counter() - t0) / reps, res, torch.cuda.max_memory_allocated()
 
-    dt, ok, mem = timed(ckpt)
-    dt_all, ok_all, mem_all = timed(p.steps)
+    dt, (L32, gI32, gk32), mem = timed(ckpt, rt.F32)
+    dt_all, (_, _, gk_all), mem_all = timed(p.steps, rt.F32)
+    dt64, (L64, gI64, gk64), mem64 = timed(ckpt, rt.F64)
+    nrm = lambda a, b: float((a.double() - b).abs().max() / b.abs().max())
+    agree = {"loss": abs(L32 - L64) / abs(L64), "dL_dI0": nrm(gI32, gI64), "dL_dkappa": nrm(gk32, gk64)}
+    ok = bool(torch.isfinite(gk32).all() and torch.isfinite(gI32).all())
+    angles.free()
     mesh.free()
     log(f"  fwd+adj: {dt * 1e3:.1f} ms per pass of {p.steps} steps (checkpoints every {ckpt}); "
-        f"{dt_all * 1e3:.1f} ms with every step taped")
+        f"{dt_all * 1e3:.1f} ms with every step taped; FP64 {dt64 * 1e3:.1f} ms; FP32 vs FP64: "
+        + ", ".join(f"{k} {v:.1e}" for k, v in agree.items()))
     return {"value": N * K * p.steps / dt, "unit": "cell-angle updates/s", "ms_per_pass": dt * 1e3,
             "workload": f"adjoint_{round(N ** (1 / 3))}c_{K}a", "cells": N, "angles": K, "steps": p.steps,
             "checkpoint_every": ckpt, "dtype": "f32", "angle_order": "antipodes adjacent",
             "gradient_finite": ok, "peak_device_GB": round(mem / 1e9, 2),
             "tape_every_step": {"value": N * K * p.steps / dt_all, "ms_per_pass": dt_all * 1e3,
-                                "gradient_finite": ok_all, "peak_device_GB": round(mem_all / 1e9, 2)}}
+                                "gradient_finite": bool(torch.isfinite(gk_all).all()),
+                                "peak_device_GB": round(mem_all / 1e9, 2)},
+            "fp64": {"value": N * K * p.steps / dt64, "ms_per_pass": dt64 * 1e3, "dtype": "f64",
+                     "peak_device_GB": round(mem64 / 1e9, 2)},
+            "f32_vs_f64": agree}
 
 
 def run_plm(log):
