@@ -249,11 +249,12 @@ int rt_step_taped(rt_mesh *mesh, const rt_params *params, const rt_angles *angle
  * Voronoi gradient estimator of S10 with the geometric cell volumes, limited by
  * the Barth-Jespersen factor so that extrapolations from the centre of mass to
  * every face centroid stay within the range of the cell and its neighbours.
- * I [N][K] (device, dtype) in, grad [N][3][K] (device, dtype) out.  Needs
- * RT_MESH_PLM only for the scheme, not for this call.  The face records of 16
- * consecutive cells are staged in 64 KiB of LDS: RT_EHIP if such a block has more
- * than 655 half-faces in FP64 (1260 in FP32), about 40 faces per cell, far above
- * the ~16 of a Voronoi mesh.
+ * I [N][K] (device, dtype) in, grad [N][3][K] (device, dtype) out.  Needs a mesh
+ * uploaded with RT_MESH_PLM (RT_ESTATE otherwise): it holds the estimator's weights
+ * (one vector per half-face and one per cell, formed at upload) and the
+ * reconstruction offsets.  The upload refuses a PLM mesh whose face records of 16
+ * consecutive cells would not fit in the LDS a workgroup may use, so this call does
+ * not fail for that reason.
  */
 int rt_gradient(rt_mesh *mesh, const rt_params *params, const rt_angles *angles, const void *I, void *grad,
                 void *stream);
