@@ -160,6 +160,12 @@ k_source_kT(rt_kT_args a, int64_t nblk) {
     x = Tx;
   }
 
+  // The directions and weights are needed before the iteration and after it, not in it: read
+  // them again here (through a pointer the compiler cannot prove unchanged, so it does not keep
+  // the first copy live through the iteration) instead of holding them in registers.
+  const double *dirs_again = a.dirs, *W_again = a.W;
+  asm volatile("" : "+s"(dirs_again), "+s"(W_again));
+  ang.load(dirs_again, W_again, K, l);
   const double T4 = Tq * Tq * Tq * Tq;
   const double planck = a.a_rad * T4 * (1.0 / fourpi);
   const double Jc = (e.SI + y * e.kP * e.SG * planck) * rt_rcp(e.D);
