@@ -10,11 +10,11 @@ namespace {
 
 // Faces gathered per batch: all their neighbour-row loads are issued before any is
 // used, so one memory round trip serves U faces.  At 128^3 x 80: two faces measured ~2%
-// faster than four in FP32; the FP64 form with antipodes side by side (one 16-byte load
-// per angle pair, two waves per SIMD) runs 5% faster with three (1.91 against 2.00 ms;
-// four: 1.99).
+// faster than four in FP32.  The FP64 form with antipodes side by side ran 5% faster with
+// three (1.91 against 2.00 ms) at two waves per SIMD; since its source holds fewer values
+// (three waves) two are faster again: 1.85 ms, against 2.45 ms with three.
 template <typename T, int PAIRED> struct rt_batch {
-  static constexpr int U = PAIRED == 2 && sizeof(T) == 8 ? 3 : 2;
+  static constexpr int U = 2;
 };
 
 // MODE 0: source only (in place); 1: upwind transport (+ source); 2: reconstructed
@@ -266,15 +266,6 @@ k_step(rt_step_args a, int64_t nblk) {
   }
 
   if constexpr (MODE <= 2) {
-    if (MODE == 2 && sizeof(T) == 8) {
-      // FP64 PLM stage 2 spills at two waves per SIMD: the source reads the angle data again
-      // (through a pointer the compiler cannot prove unchanged) rather than holding the weights
-      // through the face loop, which needs only the directions.  Spill 128 -> 96 bytes per
-      // lane, 64^3 x 80 PLM step 1.412 -> 1.399 ms.
-      const double *dirs_again = a.dirs, *W_again = a.W;
-      asm volatile("" : "+s"(dirs_again), "+s"(W_again));
-      ang.load(dirs_again, W_again, K, l);
-    }
     if (a.do_source) rt_source_cell<T, LPC, APL>(a, ang, cell, l, Ic);
   }
   if constexpr (MODE >= 4) {

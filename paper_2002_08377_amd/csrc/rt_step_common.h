@@ -137,22 +137,39 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
     // lanes' partials meet in FP64.
     T sQ_ = 0, s1_ = 0, sG_ = 0, sI_ = 0;
     // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
-    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S, so pass 2 keeps
-    // only I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).
-    T I0[APL], Br[APL];
+    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S.  FP32: pass 2 keeps
+    // I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).  FP64 (LIGHT):
+    // only the incoming I is held; Gamma, r and r / Gamma^3 are formed again in the update
+    // from the same expressions (their inputs pass an empty asm so the compiler cannot reuse
+    // this pass's values: the same bits), and the weights are read again here rather than
+    // held through the caller's face loop.
+    constexpr bool LIGHT = sizeof(T) == 8;
+    T I0[LIGHT ? 1 : APL], Br[LIGHT ? 1 : APL];
+    double wq[P];
+    if constexpr (LIGHT) {
+      const double *W_again = a.W;
+      asm volatile("" : "+s"(W_again));
+#pragma unroll
+      for (int q = 0; q < P; ++q) wq[q] = ang.ok[q] ? W_again[ang.k[q]] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < P; ++q) wq[q] = ang.w[q];
+    }
     auto pass1 = [&](int q, T G) {
-      I0[q] = Ic[q];
+      if constexpr (!LIGHT) I0[q] = Ic[q];
       const T iG = rt_rcp(G);
       const T iG2 = iG * iG;
       const T G2 = G * G;
       const T r = rt_rcp(T(1) + tyc * G);
-      const T qk = (T)ang.wt(q) * iG2;
+      const T qk = (T)wq[q < P ? q : q - P] * iG2;
       sQ_ += qk;
       s1_ += qk * r;
       sG_ += qk * (G * r);
       sI_ += qk * (G2 * G2 * Ic[q] * r);
-      Ic[q] *= r;
-      Br[q] = r * iG2 * iG;
+      if constexpr (!LIGHT) {
+        Ic[q] *= r;
+        Br[q] = r * iG2 * iG;
+      }
     };
 #pragma unroll
     for (int q = 0; q < P; ++q) {
@@ -182,16 +199,36 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
     // ---- 3. per-angle implicit update, boost back; 4. radiation energy and momentum lost
     //         by the stored values, handed to the gas (eqs. 35-36) ------------------------
     double dE = 0, dFx = 0, dFy = 0, dFz = 0;
+    T tg3 = tg, tvx3 = tvx, tvy3 = tvy, tvz3 = tvz, tyc3 = tyc;
+    if constexpr (LIGHT) asm volatile("" : "+v"(tg3), "+v"(tvx3), "+v"(tvy3), "+v"(tvz3), "+v"(tyc3));
+    // the updated value of slot q (boost factor G) and, through I_in, its incoming value
+    auto update = [&](int q, T G, T &I_in) {
+      if constexpr (LIGHT) {
+        const T iG = rt_rcp(G);
+        const T iG2 = iG * iG;
+        const T r = rt_rcp(T(1) + tyc3 * G);
+        const T Ir = Ic[q] * r;
+        const T B = r * iG2 * iG;
+        I_in = Ic[q];
+        return Ir + B * ySrc;
+      } else {
+        I_in = I0[q];
+        return Ic[q] + Br[q] * ySrc;
+      }
+    };
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const T out = Ic[q] + Br[q] * ySrc;
+      const T vn = LIGHT ? tvx3 * ang.x[q] + tvy3 * ang.y[q] + tvz3 * ang.z[q] : T(0);
+      T in1;
+      const T out = update(q, tg3 * (T(1) - vn), in1);
       Ic[q] = out;
-      double wd = ang.w[q] * ((double)I0[q] - (double)out);
+      double wd = wq[q] * ((double)in1 - (double)out);
       dE += wd;
       if (PAIRED) {
-        const T out2 = Ic[q + P] + Br[q + P] * ySrc;
+        T in2;
+        const T out2 = update(q + P, tg3 * (T(1) + vn), in2);
         Ic[q + P] = out2;
-        const double wd2 = ang.w[q] * ((double)I0[q + P] - (double)out2);
+        const double wd2 = wq[q] * ((double)in2 - (double)out2);
         dE += wd2;
         wd -= wd2;  // the antipode's direction is -n
       }
