@@ -137,12 +137,13 @@ __device__ __forceinline__ void rt_source_cell(const rt_step_args &a, const Ang 
     // lanes' partials meet in FP64.
     T sQ_ = 0, s1_ = 0, sG_ = 0, sI_ = 0;
     // Per angle, with r = 1/(1 + y chi Gamma): the update of eq. 28 boosted back is
-    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S.  FP32: pass 2 keeps
-    // I r and r / Gamma^3 (and the incoming I for the bookkeeping of step 4).  FP64 (LIGHT):
-    // only the incoming I is held; Gamma, r and r / Gamma^3 are formed again in the update
-    // from the same expressions (their inputs pass an empty asm so the compiler cannot reuse
-    // this pass's values: the same bits), and the weights are read again here rather than
-    // held through the caller's face loop.
+    // I' = (Gamma^4 I + y Gamma S) r / Gamma^4 = I r + (r / Gamma^3) y S.  FP32: I r and
+    // r / Gamma^3 are kept from the sums to the update (Ic, Br), with the incoming I (I0) for
+    // the bookkeeping of step 4.  FP64 (LIGHT, to stay within three waves per SIMD): only the
+    // incoming I is held through the temperature solve; Gamma, r and r / Gamma^3 are formed
+    // again in the update by the same expressions (their inputs pass an empty asm, so the
+    // compiler cannot reuse the first values and no value changes), and the weights are read
+    // again here rather than held through the caller's face loop.
     constexpr bool LIGHT = sizeof(T) == 8;
     T I0[LIGHT ? 1 : APL], Br[LIGHT ? 1 : APL];
     double wq[P];
