@@ -297,6 +297,50 @@ def test_throughput_128c_80a_ten_steps(dtype, order, throughput_problem):
         assert err["T"] < 1e-6 * p.steps and err["etot"] < 1e-6 * p.steps and err["mom"] < 1e-6 * p.steps, err
 
 
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+@pytest.mark.parametrize("fast", [False, True])
+def test_uniform_field_stays_uniform_at_full_size(dtype, fast, throughput_problem):
+    """Free streaming of a uniform field on the moving mesh, at full size in the bench's launch
+    configuration (paired lanes, antipodes side by side): transport alone, 3 steps.  A closed
+    cell's faces carry sum_f A_f n_f = 0 and sum_f A_f (w~.n)_f = D (section 2.2 with the volume
+    update), so the charges leaving it sum to -I dt D and I' = (V I + I dt D) / (V + dt D) = I,
+    to rounding: a property of the method that needs no oracle.  Slow mesh: the recipe's
+    velocities; fast: 0.3 cbar drift with 0.03 cbar scatter, so the face term decides many
+    upwind sides.  FP64 is bounded by the tessellation's closure (1e-13 after 3 steps); the
+    FP32 form by its rounded face records (1e-5)."""
+    p, _, _ = throughput_problem
+    p = inp.with_angle_order(p, inp.adjacent_pair_order(80))
+    st = p.state
+    w, dt = st.mesh_vel, p.dt
+    if fast:
+        rng = np.random.default_rng(2024)
+        c_red = p.phys.c_red
+        w = 0.3 * c_red * np.array([1.0, 2.0, 2.0]) / 3.0 + rng.normal(0.0, 0.03 * c_red, size=(p.mesh.n_cells, 3))
+        dt = inp.courant_dt(p.mesh, c_red)
+    mesh = rt.Mesh.from_inputs(p.mesh, np.ascontiguousarray(w), k_max=80)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    assert ang.layout == rt.ANGLES_ANTIPODAL_ADJACENT
+    prm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, dt, dtype)
+    td = rt.torch_dtype(dtype)
+    I0 = 1.7
+    I = torch.full(st.I.shape, I0, dtype=td, device="cuda")
+    I2 = torch.empty_like(I)
+    vol = torch.as_tensor(np.ascontiguousarray(st.vol), device="cuda")
+    for _ in range(3):
+        rt.transport_step(mesh, prm, ang, I, I2, vol)
+        I, I2 = I2, I
+    torch.cuda.synchronize()
+    err = float((I.double() - I0).abs().max()) / I0
+    vmin = float(vol.min())
+    print(f"uniform field 128^3 x 80, 3 transport steps, {'FP64' if dtype == rt.F64 else 'FP32'}, "
+          f"{'fast' if fast else 'recipe'} mesh: max |I - I0| / I0 = {err:.2e}, min V = {vmin:.3e}")
+    ang.free()
+    mesh.free()
+    assert vmin > 0.0
+    assert err < (1e-13 if dtype == rt.F64 else 1e-5), err
+
 def test_flux_loss_and_seed_match_oracle():
     p = _prob(2, n=10, K=48)
     dp = DeviceProblem(p)
