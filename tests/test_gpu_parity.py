@@ -341,6 +341,115 @@ def test_uniform_field_stays_uniform_at_full_size(dtype, fast, throughput_proble
     assert vmin > 0.0
     assert err < (1e-13 if dtype == rt.F64 else 1e-5), err
 
+
+def _planck(phys, T):
+    return phys.a_rad * np.asarray(T) ** 4 / (4.0 * np.pi)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_equilibrium_is_a_fixed_point_of_the_step_at_full_size(dtype, throughput_problem):
+    """Gas at rest at one temperature T and the isotropic field I = a T^4 / 4 pi, with kP = kJ:
+    the fused step (bench launches, 128^3 x 80, the recipe's moving mesh, cbar = c/10) must
+    leave I, T, E_g and rho v as they are, for 3 steps.  Transport keeps a uniform field uniform
+    (closed faces, the volume update); in the source of section 2.3 the quartic's root is then
+    T^n itself, J~ = B and every comoving I~' = B, so nothing is handed to the gas.  A property
+    of the method, with no oracle."""
+    p, _, _ = throughput_problem
+    p = inp.with_angle_order(p, inp.adjacent_pair_order(80))
+    st = p.state
+    phys = inp.Physics(c_red=10.0, c_light=100.0)
+    N, K = st.I.shape
+    T0 = 1.3
+    B = float(_planck(phys, T0))
+    etot0 = st.rho * phys.cv * T0
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(phys.c_red, phys.c_light, phys.a_rad, phys.cv, p.dt, dtype)
+    td = rt.torch_dtype(dtype)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    I = torch.full((N, K), B, dtype=td, device="cuda")
+    I2 = torch.empty_like(I)
+    vol, rho, etot = d(st.vol), d(st.rho), d(etot0)
+    mom = torch.zeros((N, 3), dtype=torch.float64, device="cuda")
+    kP, ks = d(st.kP), d(st.ks)
+    T = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        rt.step(mesh, prm, ang, I, I2, vol, rho, mom, etot, kP, kP, ks, T)
+        I, I2 = I2, I
+    torch.cuda.synchronize()
+    # the FP32 form books the gas from FP32-rounded intensities: a cell's relative error in E_g
+    # (and T) is that of its radiation energy times (c/cbar) E_r / E_g, its share of the balance
+    amp = np.maximum(1.0, phys.c_light / phys.c_red * 4.0 * np.pi * B / etot0)
+    if dtype == rt.F64:
+        amp = np.ones_like(amp)
+    err = {"I": float((I.double() - B).abs().max()) / B,
+           "T": float(np.max(np.abs(T.cpu().numpy() - T0) / T0 / amp)),
+           "etot": float(np.max(np.abs(etot.cpu().numpy() - etot0) / etot0 / amp)),
+           "mom": float(mom.abs().max()) / (4.0 * np.pi * B / phys.c_red)}
+    print(f"equilibrium 128^3 x 80, 3 fused steps, {'FP64' if dtype == rt.F64 else 'FP32'}:",
+          {k: f"{v:.2e}" for k, v in err.items()})
+    ang.free()
+    mesh.free()
+    # FP32: intensities rounded to FP32 and transported with FP32 records; T and E_g within
+    # 1e-6 per step after the amplification above (the rule of the regime tests, per cell)
+    bounds = (dict(I=1e-12, T=1e-12, etot=1e-12, mom=1e-10) if dtype == rt.F64 else
+              dict(I=1e-5, T=1e-6 * 3, etot=1e-6 * 3, mom=1e-4))
+    for k, b in bounds.items():
+        assert err[k] < b, (k, err[k])
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_comoving_equilibrium_is_a_fixed_point_of_the_source_at_full_size(dtype, throughput_problem):
+    """Moving gas (|v| up to 0.05 c), each cell at its own temperature T, kP = kJ, and the lab
+    intensities of a comoving isotropic field, I_k = (a T^4 / 4 pi) / Gamma_k^4 with
+    Gamma_k = gamma (1 - v.n_k / c) (section 2.3): the implicit source at cbar = c/10 must leave
+    the intensities, T, E_g and rho v as they are (128^3 cells x 80 angles, antipodes side by
+    side).  A property of the method, with no oracle."""
+    p, _, _ = throughput_problem
+    p = inp.with_angle_order(p, inp.adjacent_pair_order(80))
+    st = p.state
+    phys = inp.Physics(c_red=10.0, c_light=100.0)
+    N, K = st.I.shape
+    rng = np.random.default_rng(7)
+    v = rng.normal(size=(N, 3))
+    v *= (0.05 * phys.c_light * rng.uniform(0.0, 1.0, N) / np.linalg.norm(v, axis=1))[:, None]
+    gam = 1.0 / np.sqrt(1.0 - np.sum(v * v, axis=1) / phys.c_light ** 2)
+    Gm = gam[:, None] * (1.0 - (v @ p.dirs.T) / phys.c_light)
+    I0 = _planck(phys, st.T)[:, None] / Gm ** 4
+    mom0 = st.rho[:, None] * v
+    etot0 = st.rho * phys.cv * st.T + 0.5 * st.rho * np.sum(v * v, axis=1)
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(phys.c_red, phys.c_light, phys.a_rad, phys.cv, p.dt, dtype)
+    td = rt.torch_dtype(dtype)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    I = d(I0).to(td).contiguous()
+    Iref = I.double().cpu().numpy()  # the stored (for FP32, rounded) field
+    rho, mom, etot, kP, ks = d(st.rho), d(mom0), d(etot0), d(st.kP), d(st.ks)
+    T = torch.zeros(N, dtype=torch.float64, device="cuda")
+    rt.source_implicit(mesh, prm, ang, I, rho, mom, etot, kP, kP, ks, T)
+    torch.cuda.synchronize()
+    Ih = I.double().cpu().numpy()
+    # FP32: a cell's gas error is its radiation's times (c/cbar) E_r / E_g (as in the step test)
+    amp = np.maximum(1.0, phys.c_light / phys.c_red * 4.0 * np.pi * _planck(phys, st.T) / etot0)
+    if dtype == rt.F64:
+        amp = np.ones_like(amp)
+    err = {"I": rel_err(Ih, Iref), "I_elem": elem_err(Ih, Iref),
+           "T_elem": float(np.max(np.abs(T.cpu().numpy() - st.T) / st.T / amp)),
+           "etot_elem": float(np.max(np.abs(etot.cpu().numpy() - etot0) / etot0 / amp)),
+           "mom_cell": vec_err(mom.cpu().numpy(), mom0, np.linalg.norm(mom0, axis=1) + 4 * np.pi * _planck(phys, st.T)
+                               / phys.c_red)}
+    print(f"comoving equilibrium 128^3 x 80, source, {'FP64' if dtype == rt.F64 else 'FP32'}:",
+          {k: f"{v:.2e}" for k, v in err.items()})
+    ang.free()
+    mesh.free()
+    bounds = (dict(I=1e-12, I_elem=1e-12, T_elem=1e-12, etot_elem=1e-12, mom_cell=1e-11) if dtype == rt.F64 else
+              dict(I=1e-5, I_elem=1e-5, T_elem=1e-6, etot_elem=1e-6, mom_cell=1e-4))
+    for k, b in bounds.items():
+        assert err[k] < b, (k, err[k])
+
 def test_flux_loss_and_seed_match_oracle():
     p = _prob(2, n=10, K=48)
     dp = DeviceProblem(p)
