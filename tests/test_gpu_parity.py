@@ -385,6 +385,58 @@ def test_charge_conserved_per_angle_at_full_size(dtype, fast, throughput_problem
     # of the FP32 updates (~1e-7) would not pass
     assert err < (1e-13 if dtype == rt.F64 else 1e-8), err
 
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_run_adjoint_is_the_transpose_of_transport_at_full_size(dtype, throughput_problem):
+    """The dot-product test of the reverse at 128^3 x 80 (antipodes side by side, the recipe's
+    moving mesh and moving gas): with zero opacities the source is the identity on I, so three
+    taped steps are the linear map T^3 of transport alone, and the run adjoint applied to y
+    must give (T^3)^T y: <T^3 x, y> = <x, (T^3)^T y> to rounding, relative to |T^3 x| |y|.
+    This covers every launch of the reverse (source reverse alone, fused transpose + source
+    reverse, transpose alone) against the forward launches, with no oracle."""
+    p, _, _ = throughput_problem
+    p = inp.with_angle_order(p, inp.adjacent_pair_order(80))
+    st = p.state
+    N, K = st.I.shape
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_ADJOINT)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, p.dt, dtype)
+    td = rt.torch_dtype(dtype)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    x = (0.5 + torch.rand((N, K), generator=gen, device="cuda", dtype=torch.float64)).to(td)
+    y = torch.randn((N, K), generator=gen, device="cuda", dtype=torch.float64).to(td)
+    vol, rho, mom, etot = d(st.vol), d(st.rho), d(st.mom), d(st.etot)
+    zero = torch.zeros(N, dtype=torch.float64, device="cuda")
+    outs, tapes, cur = [], [], x
+    for _ in range(3):
+        o = torch.empty_like(x)
+        r = torch.empty((N, rt.SRC_TAPE), dtype=torch.float64, device="cuda")
+        rt.step_taped(mesh, prm, ang, cur, o, None, vol, rho, mom, etot, zero, zero, zero, src_tape=r)
+        outs.append(o)
+        tapes.append(r)
+        cur = o
+    lhs = float((outs[-1].double() * y.double()).sum())
+    norm = float(outs[-1].double().norm() * y.double().norm())
+    lamI = y.clone()
+    lamE = torch.zeros(N, dtype=torch.float64, device="cuda")
+    lamM = torch.zeros((N, 3), dtype=torch.float64, device="cuda")
+    dk = torch.zeros(N, dtype=torch.float64, device="cuda")
+    rt.step_adjoint_run(mesh, prm, ang, outs, tapes, rho, zero, zero, zero, lamI, lamE, lamM, dk, dk)
+    rhs = float((x.double() * lamI.double()).sum())
+    torch.cuda.synchronize()
+    err = abs(lhs - rhs) / norm
+    print(f"dot-product test 128^3 x 80, 3 steps, {'FP64' if dtype == rt.F64 else 'FP32'}: <T^3 x, y> = {lhs:.15e}, "
+          f"<x, T^3' y> = {rhs:.15e}, |difference| / (|T^3 x| |y|) = {err:.2e}")
+    finite = bool(torch.isfinite(lamE).all() and torch.isfinite(lamM).all() and torch.isfinite(dk).all())
+    ang.free()
+    mesh.free()
+    assert finite
+    # a wrong transpose moves the two products apart by about |<T^3 x, y>| (~1e-4 of the norm
+    # product here); rounding leaves ~1e-20 (FP64) and ~1e-11 (FP32)
+    assert err < (1e-15 if dtype == rt.F64 else 1e-9), err
+
 def _planck(phys, T):
     return phys.a_rad * np.asarray(T) ** 4 / (4.0 * np.pi)
 
