@@ -437,6 +437,54 @@ def test_run_adjoint_is_the_transpose_of_transport_at_full_size(dtype, throughpu
     # product here); rounding leaves ~1e-20 (FP64) and ~1e-11 (FP32)
     assert err < (1e-15 if dtype == rt.F64 else 1e-9), err
 
+
+@pytest.fixture(scope="module")
+def plm_problem():
+    """The PLM workload's mesh and state at full size (64^3 cells, 80 angles), antipodes side by
+    side (the order the bench times)."""
+    p = inp.make_problem(1, steps=1)
+    return inp.with_angle_order(p, inp.adjacent_pair_order(80))
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_plm_transport_properties_at_full_size(dtype, plm_problem):
+    """PLM-VL2 transport alone, 3 steps at 64^3 x 80 on the recipe's moving mesh (section 2,
+    steps 2b-5): a uniform field stays uniform (its limited gradient is zero, and the faces
+    close), and on the recipe's field every angle's total sum_i V_i I_ik is conserved, since
+    both sides of a face reconstruct the upwind state by the same expression.  No oracle."""
+    p = plm_problem
+    st = p.state
+    N, K = st.I.shape
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_PLM)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(p.phys.c_red, p.phys.c_light, p.phys.a_rad, p.phys.cv, p.dt, dtype, rt.PLM_VL2)
+    td = rt.torch_dtype(dtype)
+    res = {}
+    for case in ("uniform", "recipe"):
+        if case == "uniform":
+            I = torch.full((N, K), 1.7, dtype=td, device="cuda")
+        else:
+            I = torch.as_tensor(np.ascontiguousarray(st.I), device="cuda").to(td).contiguous()
+        I2 = torch.empty_like(I)
+        vol = torch.as_tensor(np.ascontiguousarray(st.vol), device="cuda")
+        Q0 = (vol[:, None] * I.double()).sum(0)
+        for _ in range(3):
+            rt.transport_step(mesh, prm, ang, I, I2, vol)
+            I, I2 = I2, I
+        if case == "uniform":
+            res["uniform"] = float((I.double() - 1.7).abs().max()) / 1.7
+        else:
+            Q = (vol[:, None] * I.double()).sum(0)
+            res["charge"] = float(((Q - Q0).abs() / Q0).max())
+    torch.cuda.synchronize()
+    print(f"PLM 64^3 x 80, 3 transport steps, {'FP64' if dtype == rt.F64 else 'FP32'}:",
+          {k: f"{v:.2e}" for k, v in res.items()})
+    ang.free()
+    mesh.free()
+    assert res["uniform"] < (1e-13 if dtype == rt.F64 else 1e-5), res
+    assert res["charge"] < (1e-13 if dtype == rt.F64 else 1e-8), res
+
 def _planck(phys, T):
     return phys.a_rad * np.asarray(T) ** 4 / (4.0 * np.pi)
 
