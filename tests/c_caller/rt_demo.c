@@ -1,0 +1,245 @@
+/*
+ * A plain C caller of librtmm: no Python, no torch.  It builds a periodic cubic lattice
+ * (every cell a cube meeting its six axis neighbours; the generators drift uniformly, so
+ * faces move while every volume stays fixed), uploads it, verifies an antipodal angle set
+ * on the device and runs the library in both precision forms, checking two properties of
+ * the method that need no reference solution:
+ *   1. radiative equilibrium (gas at rest at one temperature T, I = a T^4 / 4 pi, kP = kJ)
+ *      is a fixed point of the fused step (section 2.3: the quartic's root is T^n, J~ = B);
+ *   2. transport alone conserves every angle's total sum_i V_i I_ik (section 2.2: each face's
+ *      charge leaves one cell as it enters the other) and keeps I >= 0 within the Courant
+ *      limit.
+ * Device memory comes from HIP's runtime API.  Prints one line per check and "ok" last;
+ * exit status 0 only if every check passes.
+ */
+#include <hip/hip_runtime_api.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "rtmm.h"
+
+#define N_SIDE 6
+#define N_CELLS (N_SIDE * N_SIDE * N_SIDE)
+#define N_FACES (3 * N_CELLS)
+#define K_ANG 8
+#define PI 3.14159265358979323846
+
+static int failures = 0;
+
+#define RT_CHECK(call)                                                                        \
+  do {                                                                                        \
+    int rc_ = (call);                                                                         \
+    if (rc_ != RT_OK) {                                                                       \
+      printf("FAIL %s: %s (%s)\n", #call, rt_strerror(rc_), rt_last_error());               \
+      exit(2);                                                                                \
+    }                                                                                         \
+  } while (0)
+
+#define HIP_CHECK(call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      printf("FAIL %s: %s\n", #call, hipGetErrorString(e_));                                  \
+      exit(2);                                                                                \
+    }                                                                                         \
+  } while (0)
+
+static void expect(int ok, const char *what, double value, double bound) {
+  printf("%s %s: %.3e (bound %.1e)\n", ok ? "pass" : "FAIL", what, value, bound);
+  if (!ok) ++failures;
+}
+
+static void *dev_copy(const void *host, size_t bytes) {
+  void *d = NULL;
+  HIP_CHECK(hipMalloc(&d, bytes));
+  HIP_CHECK(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+  return d;
+}
+
+/* Intensities of the run's storage type from doubles (FP32: rounded). */
+static void *dev_intensities(const double *I, int dtype) {
+  const size_t n = (size_t)N_CELLS * K_ANG;
+  if (dtype == RT_F64) return dev_copy(I, n * sizeof(double));
+  float *f = (float *)malloc(n * sizeof(float));
+  for (size_t i = 0; i < n; ++i) f[i] = (float)I[i];
+  void *d = dev_copy(f, n * sizeof(float));
+  free(f);
+  return d;
+}
+
+static void host_intensities(double *I, const void *d, int dtype) {
+  const size_t n = (size_t)N_CELLS * K_ANG;
+  if (dtype == RT_F64) {
+    HIP_CHECK(hipMemcpy(I, d, n * sizeof(double), hipMemcpyDeviceToHost));
+    return;
+  }
+  float *f = (float *)malloc(n * sizeof(float));
+  HIP_CHECK(hipMemcpy(f, d, n * sizeof(float), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < n; ++i) I[i] = f[i];
+  free(f);
+}
+
+int main(void) {
+  const double box = 1.0, h = box / N_SIDE;
+  static double gen[N_CELLS][3], vel[N_CELLS][3], vol[N_CELLS];
+  static int32_t fcell[N_FACES][2];
+  static int8_t fshift[N_FACES][3];
+  static double farea[N_FACES], fnorm[N_FACES][3], fcen[N_FACES][3];
+  for (int z = 0; z < N_SIDE; ++z)
+    for (int y = 0; y < N_SIDE; ++y)
+      for (int x = 0; x < N_SIDE; ++x) {
+        const int c[3] = {x, y, z};
+        const int i = x + N_SIDE * (y + N_SIDE * z);
+        for (int a = 0; a < 3; ++a) {
+          gen[i][a] = (c[a] + 0.5) * h;
+          vel[i][a] = a == 0 ? 0.10 : a == 1 ? 0.05 : 0.0; /* uniform drift: D = 0 */
+        }
+        vol[i] = h * h * h;
+        for (int a = 0; a < 3; ++a) { /* the face towards the + neighbour along axis a */
+          int cn[3] = {x, y, z};
+          cn[a] = (c[a] + 1) % N_SIDE;
+          const int f = 3 * i + a;
+          fcell[f][0] = i;
+          fcell[f][1] = cn[0] + N_SIDE * (cn[1] + N_SIDE * cn[2]);
+          for (int b = 0; b < 3; ++b) {
+            fshift[f][b] = (int8_t)(b == a && c[a] + 1 == N_SIDE);
+            fnorm[f][b] = b == a ? 1.0 : 0.0;
+            fcen[f][b] = gen[i][b] + (b == a ? 0.5 * h : 0.0);
+          }
+          farea[f] = h * h;
+        }
+      }
+  rt_mesh *mesh = NULL;
+  RT_CHECK(rt_mesh_upload(&mesh, N_CELLS, N_FACES, K_ANG, 0, &gen[0][0], &gen[0][0], vol, &vel[0][0],
+                          &fcell[0][0], &fshift[0][0], farea, &fnorm[0][0], &fcen[0][0], box, NULL));
+
+  /* eight diagonal directions, each antipode K/2 further on, equal weights */
+  double dir[K_ANG][3], w[K_ANG];
+  const double s = 1.0 / sqrt(3.0);
+  for (int k = 0; k < K_ANG / 2; ++k) {
+    dir[k][0] = s;
+    dir[k][1] = (k & 1) ? -s : s;
+    dir[k][2] = (k & 2) ? -s : s;
+    for (int b = 0; b < 3; ++b) dir[k + K_ANG / 2][b] = -dir[k][b];
+  }
+  for (int k = 0; k < K_ANG; ++k) w[k] = 1.0 / K_ANG;
+  int32_t layout = -1;
+  RT_CHECK(rt_angles_layout(K_ANG, &dir[0][0], w, &layout));
+  expect(layout == RT_ANGLES_ANTIPODAL, "angle set detected as antipodal (K/2 order)", (double)layout, 1.0);
+  rt_angles ang;
+  ang.K = K_ANG;
+  ang.layout = layout;
+  ang.dir = (const double *)dev_copy(dir, sizeof dir);
+  ang.weight = (const double *)dev_copy(w, sizeof w);
+  RT_CHECK(rt_angles_check(&ang, NULL));
+
+  const double c_red = 10.0, c_light = 100.0, a_rad = 1.0, cv = 1.5, T0 = 1.2;
+  const double dt = 0.2 * h / c_red;
+  const double B = a_rad * pow(T0, 4) / (4.0 * PI);
+  static double I[N_CELLS * K_ANG], Ih[N_CELLS * K_ANG], rho[N_CELLS], mom[N_CELLS][3], etot[N_CELLS],
+      kap[N_CELLS], ks[N_CELLS], Tn[N_CELLS];
+  for (int i = 0; i < N_CELLS; ++i) {
+    rho[i] = 0.5 + 0.01 * i;
+    for (int a = 0; a < 3; ++a) mom[i][a] = 0.0;
+    etot[i] = rho[i] * cv * T0;
+    kap[i] = 0.5 + 0.02 * (i % 17);
+    ks[i] = 0.3;
+  }
+  const int dtypes[2] = {RT_F64, RT_F32};
+  for (int t = 0; t < 2; ++t) {
+    const int dtype = dtypes[t];
+    const char *form = dtype == RT_F64 ? "FP64" : "FP32";
+    char what[160];
+    rt_params prm = {c_red, c_light, a_rad, cv, dt, dtype, RT_UPWIND1};
+
+    /* 1. equilibrium through 5 fused steps */
+    for (int i = 0; i < N_CELLS * K_ANG; ++i) I[i] = B;
+    void *dI = dev_intensities(I, dtype), *dI2 = dev_intensities(I, dtype);
+    double *dvol = (double *)dev_copy(vol, sizeof vol), *drho = (double *)dev_copy(rho, sizeof rho);
+    double *dmom = (double *)dev_copy(mom, sizeof mom), *detot = (double *)dev_copy(etot, sizeof etot);
+    double *dk = (double *)dev_copy(kap, sizeof kap), *dks = (double *)dev_copy(ks, sizeof ks);
+    double *dT = NULL;
+    HIP_CHECK(hipMalloc((void **)&dT, sizeof Tn));
+    for (int n = 0; n < 5; ++n) {
+      RT_CHECK(rt_step(mesh, &prm, &ang, dI, dI2, dvol, drho, dmom, detot, dk, dk, dks, dT, NULL));
+      void *tmp = dI;
+      dI = dI2;
+      dI2 = tmp;
+    }
+    HIP_CHECK(hipDeviceSynchronize());
+    static double e1[N_CELLS], m1[N_CELLS][3];
+    host_intensities(Ih, dI, dtype);
+    HIP_CHECK(hipMemcpy(Tn, dT, sizeof Tn, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(e1, detot, sizeof e1, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(m1, dmom, sizeof m1, hipMemcpyDeviceToHost));
+    double eI = 0, eT = 0, eE = 0, eM = 0;
+    for (int i = 0; i < N_CELLS * K_ANG; ++i) eI = fmax(eI, fabs(Ih[i] - B) / B);
+    for (int i = 0; i < N_CELLS; ++i) {
+      eT = fmax(eT, fabs(Tn[i] - T0) / T0);
+      eE = fmax(eE, fabs(e1[i] - etot[i]) / etot[i]);
+      for (int a = 0; a < 3; ++a) eM = fmax(eM, fabs(m1[i][a]) / (4.0 * PI * B / c_red));
+    }
+    /* FP32: intensities rounded to FP32; the gas is booked from them, so its relative error
+       is theirs amplified by (c/cbar) E_r / E_g (at most ~23 here), over 5 steps */
+    const double bI = dtype == RT_F64 ? 1e-13 : 5e-6, bG = dtype == RT_F64 ? 1e-13 : 1e-4;
+    snprintf(what, sizeof what, "%s equilibrium kept by 5 fused steps: max |I - B| / B", form);
+    expect(eI < bI, what, eI, bI);
+    snprintf(what, sizeof what, "%s equilibrium: max |T - T0| / T0", form);
+    expect(eT < bG, what, eT, bG);
+    snprintf(what, sizeof what, "%s equilibrium: max |E_g - E_g0| / E_g0", form);
+    expect(eE < bG, what, eE, bG);
+    snprintf(what, sizeof what, "%s equilibrium: max |rho v| / (4 pi B / cbar)", form);
+    expect(eM < bG, what, eM, bG);
+
+    /* 2. transport alone of a non-uniform field: per-angle totals and positivity */
+    for (int i = 0; i < N_CELLS; ++i)
+      for (int k = 0; k < K_ANG; ++k) I[i * K_ANG + k] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * k) + (i == 17 ? 5.0 : 0.0);
+    HIP_CHECK(hipFree(dI));
+    dI = dev_intensities(I, dtype);
+    host_intensities(I, dI, dtype); /* the stored (for FP32, rounded) field */
+    double Q0[K_ANG] = {0}, Q[K_ANG] = {0};
+    for (int i = 0; i < N_CELLS; ++i)
+      for (int k = 0; k < K_ANG; ++k) Q0[k] += vol[i] * I[i * K_ANG + k];
+    HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+    for (int n = 0; n < 4; ++n) {
+      RT_CHECK(rt_transport_step(mesh, &prm, &ang, dI, dI2, dvol, NULL));
+      void *tmp = dI;
+      dI = dI2;
+      dI2 = tmp;
+    }
+    HIP_CHECK(hipDeviceSynchronize());
+    static double v1[N_CELLS];
+    host_intensities(Ih, dI, dtype);
+    HIP_CHECK(hipMemcpy(v1, dvol, sizeof v1, hipMemcpyDeviceToHost));
+    double eQ = 0, imin = 1e300;
+    for (int i = 0; i < N_CELLS; ++i)
+      for (int k = 0; k < K_ANG; ++k) {
+        Q[k] += v1[i] * Ih[i * K_ANG + k];
+        imin = fmin(imin, Ih[i * K_ANG + k]);
+      }
+    for (int k = 0; k < K_ANG; ++k) eQ = fmax(eQ, fabs(Q[k] - Q0[k]) / Q0[k]);
+    const double bQ = dtype == RT_F64 ? 1e-13 : 1e-6;
+    snprintf(what, sizeof what, "%s transport, 4 steps: max_k |Q_k - Q0_k| / Q0_k", form);
+    expect(eQ < bQ, what, eQ, bQ);
+    snprintf(what, sizeof what, "%s transport keeps I >= 0: min I", form);
+    expect(imin >= 0.0, what, imin, 0.0);
+
+    HIP_CHECK(hipFree(dI));
+    HIP_CHECK(hipFree(dI2));
+    HIP_CHECK(hipFree(dvol));
+    HIP_CHECK(hipFree(drho));
+    HIP_CHECK(hipFree(dmom));
+    HIP_CHECK(hipFree(detot));
+    HIP_CHECK(hipFree(dk));
+    HIP_CHECK(hipFree(dks));
+    HIP_CHECK(hipFree(dT));
+  }
+  RT_CHECK(rt_angles_release(&ang));
+  HIP_CHECK(hipFree((void *)ang.dir));
+  HIP_CHECK(hipFree((void *)ang.weight));
+  RT_CHECK(rt_mesh_free(mesh));
+  printf("%s\n", failures ? "bad" : "ok");
+  return failures ? 1 : 0;
+}
