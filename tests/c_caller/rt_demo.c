@@ -6,9 +6,16 @@
  * the method that need no reference solution:
  *   1. radiative equilibrium (gas at rest at one temperature T, I = a T^4 / 4 pi, kP = kJ)
  *      is a fixed point of the fused step (section 2.3: the quartic's root is T^n, J~ = B);
- *   2. transport alone conserves every angle's total sum_i V_i I_ik (section 2.2: each face's
- *      charge leaves one cell as it enters the other) and keeps I >= 0 within the Courant
- *      limit.
+ *   2. away from equilibrium the fused step keeps sum V (E_g + (c/cbar) E_r) and
+ *      sum V (rho v + F_r / (c cbar)) (section 2.3.1), read through rt_diagnostics;
+ *   3. transport alone, first order and PLM-VL2, conserves every angle's total
+ *      sum_i V_i I_ik (section 2.2: each face's charge leaves one cell as it enters the
+ *      other), first order keeps I >= 0 within the Courant limit, and PLM keeps a uniform
+ *      field uniform;
+ *   4. the angle moments of an isotropic field are E_r = 4 pi B, F_r = 0, P_r = E_r / 3 (the
+ *      eight cube diagonals integrate n n exactly; section 2.1);
+ *   5. with zero opacities the step is transport alone, a linear map T, and rt_step_adjoint
+ *      must apply its transpose: <T x, y> = <x, T' y> to rounding.
  * Device memory comes from HIP's runtime API.  Prints one line per check and "ok" last;
  * exit status 0 only if every check passes.
  */
@@ -112,8 +119,10 @@ int main(void) {
         }
       }
   rt_mesh *mesh = NULL;
-  RT_CHECK(rt_mesh_upload(&mesh, N_CELLS, N_FACES, K_ANG, 0, &gen[0][0], &gen[0][0], vol, &vel[0][0],
+  RT_CHECK(rt_mesh_upload(&mesh, N_CELLS, N_FACES, K_ANG, RT_MESH_PLM | RT_MESH_ADJOINT, &gen[0][0], &gen[0][0], vol,
+                          &vel[0][0],
                           &fcell[0][0], &fshift[0][0], farea, &fnorm[0][0], &fcen[0][0], box, NULL));
+  const double c_red = 10.0, c_light = 100.0;
 
   /* eight diagonal directions, each antipode K/2 further on, equal weights */
   double dir[K_ANG][3], w[K_ANG];
@@ -135,7 +144,7 @@ int main(void) {
   ang.weight = (const double *)dev_copy(w, sizeof w);
   RT_CHECK(rt_angles_check(&ang, NULL));
 
-  const double c_red = 10.0, c_light = 100.0, a_rad = 1.0, cv = 1.5, T0 = 1.2;
+  const double a_rad = 1.0, cv = 1.5, T0 = 1.2;
   const double dt = 0.2 * h / c_red;
   const double B = a_rad * pow(T0, 4) / (4.0 * PI);
   static double I[N_CELLS * K_ANG], Ih[N_CELLS * K_ANG], rho[N_CELLS], mom[N_CELLS][3], etot[N_CELLS],
@@ -193,7 +202,7 @@ int main(void) {
     snprintf(what, sizeof what, "%s equilibrium: max |rho v| / (4 pi B / cbar)", form);
     expect(eM < bG, what, eM, bG);
 
-    /* 2. transport alone of a non-uniform field: per-angle totals and positivity */
+    /* 3a. first-order transport alone of a non-uniform field: per-angle totals, positivity */
     for (int i = 0; i < N_CELLS; ++i)
       for (int k = 0; k < K_ANG; ++k) I[i * K_ANG + k] = 1.0 + 0.5 * sin(0.7 * i + 1.3 * k) + (i == 17 ? 5.0 : 0.0);
     HIP_CHECK(hipFree(dI));
@@ -225,6 +234,165 @@ int main(void) {
     expect(eQ < bQ, what, eQ, bQ);
     snprintf(what, sizeof what, "%s transport keeps I >= 0: min I", form);
     expect(imin >= 0.0, what, imin, 0.0);
+
+    /* 3b. PLM-VL2 transport: a uniform field stays uniform; the recipe field's totals */
+    {
+      rt_params plm = prm;
+      plm.scheme = RT_PLM_VL2;
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) Ih[i] = 1.7;
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(Ih, dtype);
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      for (int n = 0; n < 4; ++n) {
+        RT_CHECK(rt_transport_step(mesh, &plm, &ang, dI, dI2, dvol, NULL));
+        void *tmp = dI;
+        dI = dI2;
+        dI2 = tmp;
+      }
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Ih, dI, dtype);
+      double eU = 0;
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) eU = fmax(eU, fabs(Ih[i] - 1.7) / 1.7);
+      const double bU = dtype == RT_F64 ? 1e-13 : 5e-6;
+      snprintf(what, sizeof what, "%s PLM transport, 4 steps, uniform field: max |I - I0| / I0", form);
+      expect(eU < bU, what, eU, bU);
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(I, dtype); /* I holds the stored non-uniform field of check 3 */
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      for (int n = 0; n < 4; ++n) {
+        RT_CHECK(rt_transport_step(mesh, &plm, &ang, dI, dI2, dvol, NULL));
+        void *tmp = dI;
+        dI = dI2;
+        dI2 = tmp;
+      }
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Ih, dI, dtype);
+      HIP_CHECK(hipMemcpy(v1, dvol, sizeof v1, hipMemcpyDeviceToHost));
+      double Qp[K_ANG] = {0}, eP = 0;
+      for (int i = 0; i < N_CELLS; ++i)
+        for (int k = 0; k < K_ANG; ++k) Qp[k] += v1[i] * Ih[i * K_ANG + k];
+      for (int k = 0; k < K_ANG; ++k) eP = fmax(eP, fabs(Qp[k] - Q0[k]) / Q0[k]);
+      snprintf(what, sizeof what, "%s PLM transport, 4 steps: max_k |Q_k - Q0_k| / Q0_k", form);
+      expect(eP < bQ, what, eP, bQ);
+    }
+
+    /* 4. moments of the isotropic field B */
+    {
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) Ih[i] = B;
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(Ih, dtype);
+      host_intensities(Ih, dI, dtype);
+      const double Bs = Ih[0]; /* B as stored */
+      double *dmo = NULL;
+      static double mo[N_CELLS][10];
+      HIP_CHECK(hipMalloc((void **)&dmo, sizeof mo));
+      RT_CHECK(rt_moments(mesh, &prm, &ang, dI, dmo, NULL));
+      HIP_CHECK(hipMemcpy(mo, dmo, sizeof mo, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipFree(dmo));
+      const double E = 4.0 * PI * Bs;
+      double eE0 = 0, eF = 0, eP2 = 0;
+      for (int i = 0; i < N_CELLS; ++i) {
+        eE0 = fmax(eE0, fabs(mo[i][0] - E) / E);
+        for (int a = 1; a <= 3; ++a) eF = fmax(eF, fabs(mo[i][a]) / (c_light * E));
+        for (int a = 4; a <= 6; ++a) eP2 = fmax(eP2, fabs(mo[i][a] - E / 3.0) / E);
+        for (int a = 7; a <= 9; ++a) eP2 = fmax(eP2, fabs(mo[i][a]) / E);
+      }
+      snprintf(what, sizeof what, "%s moments of an isotropic field: max |E_r - 4 pi B| / E_r", form);
+      expect(eE0 < 1e-14, what, eE0, 1e-14);
+      snprintf(what, sizeof what, "%s moments: max |F_r| / (c E_r)", form);
+      expect(eF < 1e-14, what, eF, 1e-14);
+      snprintf(what, sizeof what, "%s moments: max |P_r - E_r I / 3| / E_r", form);
+      expect(eP2 < 1e-14, what, eP2, 1e-14);
+    }
+
+    /* 2. energy and momentum balance of fused steps away from equilibrium */
+    {
+      for (int i = 0; i < N_CELLS; ++i)
+        for (int k = 0; k < K_ANG; ++k) Ih[i * K_ANG + k] = B * (1.0 + 0.4 * sin(0.3 * i + 0.9 * k));
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(Ih, dtype);
+      static double m0[N_CELLS][3];
+      for (int i = 0; i < N_CELLS; ++i)
+        for (int a = 0; a < 3; ++a) m0[i][a] = rho[i] * 0.3 * sin(1.1 * i + a);
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(dmom, m0, sizeof m0, hipMemcpyHostToDevice));
+      static double e0[N_CELLS];
+      for (int i = 0; i < N_CELLS; ++i)
+        e0[i] = etot[i] + 0.5 * (m0[i][0] * m0[i][0] + m0[i][1] * m0[i][1] + m0[i][2] * m0[i][2]) / rho[i];
+      HIP_CHECK(hipMemcpy(detot, e0, sizeof e0, hipMemcpyHostToDevice));
+      double d0[RT_NDIAG], d1[RT_NDIAG];
+      RT_CHECK(rt_diagnostics(mesh, &prm, &ang, dI, dvol, detot, dmom, d0, NULL));
+      for (int n = 0; n < 3; ++n) {
+        RT_CHECK(rt_step(mesh, &prm, &ang, dI, dI2, dvol, drho, dmom, detot, dk, dk, dks, NULL, NULL));
+        void *tmp = dI;
+        dI = dI2;
+        dI2 = tmp;
+      }
+      RT_CHECK(rt_diagnostics(mesh, &prm, &ang, dI, dvol, detot, dmom, d1, NULL));
+      const double Et0 = d0[0] + d0[1], Et1 = d1[0] + d1[1];
+      double eMom = 0;
+      for (int a = 0; a < 3; ++a) eMom = fmax(eMom, fabs((d1[2 + a] + d1[5 + a]) - (d0[2 + a] + d0[5 + a])));
+      eMom /= Et0 / c_light;
+      const double eEn = fabs(Et1 - Et0) / Et0;
+      /* FP32: the gas is booked from the stored values, but FP32 transport moves each
+         angle's total by ~1e-9 */
+      const double bB = dtype == RT_F64 ? 1e-13 : 1e-7;
+      snprintf(what, sizeof what, "%s 3 fused steps: |change of sum V (E_g + (c/cbar) E_r)| / total", form);
+      expect(eEn < bB, what, eEn, bB);
+      snprintf(what, sizeof what, "%s 3 fused steps: |change of sum V (rho v + F_r/(c cbar))| / (total energy / c)",
+               form);
+      expect(eMom < bB, what, eMom, bB);
+    }
+
+    /* 5. the per-step adjoint at zero opacity is the transpose of transport */
+    {
+      static double x[N_CELLS * K_ANG], y[N_CELLS * K_ANG], Tx[N_CELLS * K_ANG], Ty[N_CELLS * K_ANG];
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) {
+        x[i] = 1.0 + 0.5 * sin(0.37 * i);
+        y[i] = cos(0.71 * i);
+      }
+      double *zero = NULL;
+      HIP_CHECK(hipMalloc((void **)&zero, sizeof vol));
+      HIP_CHECK(hipMemset(zero, 0, sizeof vol));
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(x, dtype);
+      host_intensities(x, dI, dtype);
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(dmom, mom, sizeof mom, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(detot, etot, sizeof etot, hipMemcpyHostToDevice));
+      RT_CHECK(rt_step(mesh, &prm, &ang, dI, dI2, dvol, drho, dmom, detot, zero, zero, zero, NULL, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Tx, dI2, dtype);
+      /* the adjoint takes I* (the source input: with zero opacities, the step's output) and
+         the start-of-step gas and volume */
+      void *dlam = dev_intensities(y, dtype);
+      host_intensities(y, dlam, dtype);
+      double *dlE = NULL, *dlM = NULL;
+      HIP_CHECK(hipMalloc((void **)&dlE, sizeof vol));
+      HIP_CHECK(hipMalloc((void **)&dlM, sizeof mom));
+      HIP_CHECK(hipMemset(dlE, 0, sizeof vol));
+      HIP_CHECK(hipMemset(dlM, 0, sizeof mom));
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      RT_CHECK(rt_step_adjoint(mesh, &prm, &ang, dI2, dvol, drho, dmom, detot, zero, zero, zero, dlam, dlE, dlM, NULL,
+                               NULL, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Ty, dlam, dtype);
+      double lhs = 0, rhs = 0, nx = 0, ny = 0;
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) {
+        lhs += Tx[i] * y[i];
+        rhs += x[i] * Ty[i];
+        nx += Tx[i] * Tx[i];
+        ny += y[i] * y[i];
+      }
+      const double eD = fabs(lhs - rhs) / sqrt(nx * ny);
+      const double bD = dtype == RT_F64 ? 1e-14 : 1e-6;
+      snprintf(what, sizeof what, "%s adjoint at zero opacity: |<T x, y> - <x, T' y>| / (|T x| |y|)", form);
+      expect(eD < bD, what, eD, bD);
+      HIP_CHECK(hipFree(dlam));
+      HIP_CHECK(hipFree(dlE));
+      HIP_CHECK(hipFree(dlM));
+      HIP_CHECK(hipFree(zero));
+    }
 
     HIP_CHECK(hipFree(dI));
     HIP_CHECK(hipFree(dI2));

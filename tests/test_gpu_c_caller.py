@@ -2,10 +2,14 @@
 
 tests/c_caller/rt_demo.c (built by build() with gcc against include/rtmm.h, librtmm.so
 and HIP's runtime library) uploads a periodic cubic lattice whose generators drift,
-verifies an antipodal angle set on the device, and runs both precision forms: radiative
-equilibrium must survive 5 fused steps (section 2.3: the quartic's root is T^n), and
-transport alone must conserve every angle's total and keep I >= 0 (section 2.2).  The
-program prints one line per check and "ok" last."""
+verifies an antipodal angle set on the device, and runs both precision forms through the
+ABI alone: radiative equilibrium survives 5 fused steps (section 2.3: the quartic's root is
+T^n); fused steps away from equilibrium keep the energy and momentum totals that
+rt_diagnostics reports (section 2.3.1); first-order and PLM-VL2 transport conserve every
+angle's total (first order keeps I >= 0, PLM keeps a uniform field uniform; section 2.2);
+rt_moments gives E_r = 4 pi B, F_r = 0, P_r = E_r/3 for an isotropic field (section 2.1);
+and at zero opacity rt_step_adjoint is the transpose of the step.  The program prints one
+line per check and "ok" last."""
 import os
 import subprocess
 
@@ -25,4 +29,4 @@ def test_c_program_runs_the_step_on_the_gpu():
     assert r.returncode == 0, r.stdout + r.stderr
     lines = r.stdout.strip().splitlines()
     assert lines[-1] == "ok"
-    assert sum(line.startswith("pass ") for line in lines) == 13, r.stdout
+    assert sum(line.startswith("pass ") for line in lines) == 29, r.stdout
