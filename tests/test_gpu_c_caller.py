@@ -10,6 +10,7 @@ angle's total (first order keeps I >= 0, PLM keeps a uniform field uniform; sect
 rt_moments gives E_r = 4 pi B, F_r = 0, P_r = E_r/3 for an isotropic field (section 2.1);
 and at zero opacity rt_step_adjoint is the transpose of the step.  The program prints one
 line per check and "ok" last."""
+import importlib.util
 import os
 import subprocess
 
@@ -21,8 +22,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 EXE = os.path.join(HERE, "c_caller", "rt_demo")
 
 
+def _build():
+    """build() makes the program; where it has not run, compile it here (gcc, under a second)."""
+    spec = importlib.util.spec_from_file_location("rt_demo_build", os.path.join(HERE, "c_caller", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.build_demo()
+
+
 def test_c_program_runs_the_step_on_the_gpu():
-    assert os.path.exists(EXE), "tests/c_caller/rt_demo is not built: run __graft_entry__.build()"
+    if not os.path.exists(EXE):
+        print("building", _build(), flush=True)
     print("running", EXE, flush=True)
     r = subprocess.run([EXE], capture_output=True, text=True, timeout=120)
     print(r.stdout)
