@@ -15,7 +15,10 @@
  *   4. the angle moments of an isotropic field are E_r = 4 pi B, F_r = 0, P_r = E_r / 3 (the
  *      eight cube diagonals integrate n n exactly; section 2.1);
  *   5. with zero opacities the step is transport alone, a linear map T, and rt_step_adjoint
- *      must apply its transpose: <T x, y> = <x, T' y> to rounding.
+ *      must apply its transpose: <T x, y> = <x, T' y> to rounding;
+ *   6. the multigroup and kappa(T) steps keep equilibrium too; rt_flux_loss_noalloc gives
+ *      rt_flux_loss's loss and seed bit for bit, and an isotropic field's loss is zero; the
+ *      limited gradient of a linear field is exact away from the periodic wrap.
  * Device memory comes from HIP's runtime API.  Prints one line per check and "ok" last;
  * exit status 0 only if every check passes.
  */
@@ -392,6 +395,181 @@ int main(void) {
       HIP_CHECK(hipFree(dlE));
       HIP_CHECK(hipFree(dlM));
       HIP_CHECK(hipFree(zero));
+    }
+
+    /* 6. the extension steps at equilibrium, the flux loss and the limited gradient */
+    {
+      /* 6a. multigroup: 3 groups of weights 0.2, 0.3, 0.5, each at B, kP_j = kJ_j */
+      enum { G = 3 };
+      const double wg[G] = {0.2, 0.3, 0.5};
+      static double Ig[G * N_CELLS * K_ANG], kg[G * N_CELLS], ksg[G * N_CELLS];
+      for (int i = 0; i < G * N_CELLS * K_ANG; ++i) Ig[i] = B;
+      for (int j = 0; j < G; ++j)
+        for (int i = 0; i < N_CELLS; ++i) {
+          kg[j * N_CELLS + i] = kap[i] * (0.5 + j);
+          ksg[j * N_CELLS + i] = 0.3 * (j + 1);
+        }
+      const size_t nb = (size_t)G * N_CELLS * K_ANG * (dtype == RT_F64 ? sizeof(double) : sizeof(float));
+      void *dG1 = NULL, *dG2 = NULL;
+      HIP_CHECK(hipMalloc(&dG1, nb));
+      HIP_CHECK(hipMalloc(&dG2, nb));
+      for (int j = 0; j < G; ++j) {
+        void *part = dev_intensities(Ig + (size_t)j * N_CELLS * K_ANG, dtype);
+        HIP_CHECK(hipMemcpy((char *)dG1 + j * nb / G, part, nb / G, hipMemcpyDeviceToDevice));
+        HIP_CHECK(hipFree(part));
+      }
+      host_intensities(Ih, dG1, dtype);
+      const double Bs = Ih[0];
+      double *dwg = (double *)dev_copy(wg, sizeof wg), *dkg = (double *)dev_copy(kg, sizeof kg);
+      double *dksg = (double *)dev_copy(ksg, sizeof ksg);
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(dmom, mom, sizeof mom, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(detot, etot, sizeof etot, hipMemcpyHostToDevice));
+      for (int n = 0; n < 3; ++n) {
+        RT_CHECK(rt_step_mg(mesh, &prm, &ang, G, dwg, dG1, dG2, dvol, drho, dmom, detot, dkg, dkg, dksg, NULL, NULL));
+        void *tmp = dG1;
+        dG1 = dG2;
+        dG2 = tmp;
+      }
+      HIP_CHECK(hipDeviceSynchronize());
+      double eIg = 0;
+      for (int j = 0; j < G; ++j) {
+        host_intensities(Ih, (char *)dG1 + j * nb / G, dtype);
+        for (int i = 0; i < N_CELLS * K_ANG; ++i) eIg = fmax(eIg, fabs(Ih[i] - Bs) / Bs);
+      }
+      static double e2[N_CELLS], m2[N_CELLS][3];
+      HIP_CHECK(hipMemcpy(e2, detot, sizeof e2, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(m2, dmom, sizeof m2, hipMemcpyDeviceToHost));
+      double eEg = 0, eMg = 0;
+      for (int i = 0; i < N_CELLS; ++i) {
+        eEg = fmax(eEg, fabs(e2[i] - etot[i]) / etot[i]);
+        for (int a = 0; a < 3; ++a) eMg = fmax(eMg, fabs(m2[i][a]) / (4.0 * PI * B / c_red));
+      }
+      const double bI2 = dtype == RT_F64 ? 1e-13 : 5e-6, bG2 = dtype == RT_F64 ? 1e-13 : 1e-4;
+      snprintf(what, sizeof what, "%s multigroup equilibrium, 3 fused steps: max |I_g - B| / B", form);
+      expect(eIg < bI2, what, eIg, bI2);
+      snprintf(what, sizeof what, "%s multigroup equilibrium: max |E_g - E_g0| / E_g0", form);
+      expect(eEg < bG2, what, eEg, bG2);
+      snprintf(what, sizeof what, "%s multigroup equilibrium: max |rho v| / (4 pi B / cbar)", form);
+      expect(eMg < bG2, what, eMg, bG2);
+      HIP_CHECK(hipFree(dG1));
+      HIP_CHECK(hipFree(dG2));
+      HIP_CHECK(hipFree(dwg));
+      HIP_CHECK(hipFree(dkg));
+      HIP_CHECK(hipFree(dksg));
+
+      /* 6b. kappa(T) = kappa0 (T / 1)^-3.5 (Kramers-like), kP = kJ, at B */
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) Ih[i] = B;
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(Ih, dtype);
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(dmom, mom, sizeof mom, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(detot, etot, sizeof etot, hipMemcpyHostToDevice));
+      for (int n = 0; n < 3; ++n) {
+        RT_CHECK(rt_step_kT(mesh, &prm, &ang, dI, dI2, dvol, drho, dmom, detot, dk, dk, dks, 1.0, -3.5, -3.5, NULL,
+                            NULL));
+        void *tmp = dI;
+        dI = dI2;
+        dI2 = tmp;
+      }
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Ih, dI, dtype);
+      HIP_CHECK(hipMemcpy(e2, detot, sizeof e2, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(m2, dmom, sizeof m2, hipMemcpyDeviceToHost));
+      double eIk = 0, eEk = 0, eMk = 0;
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) eIk = fmax(eIk, fabs(Ih[i] - Bs) / Bs);
+      for (int i = 0; i < N_CELLS; ++i) {
+        eEk = fmax(eEk, fabs(e2[i] - etot[i]) / etot[i]);
+        for (int a = 0; a < 3; ++a) eMk = fmax(eMk, fabs(m2[i][a]) / (4.0 * PI * B / c_red));
+      }
+      snprintf(what, sizeof what, "%s kappa(T) equilibrium, 3 fused steps: max |I - B| / B", form);
+      expect(eIk < bI2, what, eIk, bI2);
+      snprintf(what, sizeof what, "%s kappa(T) equilibrium: max |E_g - E_g0| / E_g0", form);
+      expect(eEk < bG2, what, eEk, bG2);
+      snprintf(what, sizeof what, "%s kappa(T) equilibrium: max |rho v| / (4 pi B / cbar)", form);
+      expect(eMk < bG2, what, eMk, bG2);
+
+      /* 6c. the flux loss: the allocation-free call gives the same bits; an isotropic field
+         carries no flux through any face */
+      static double u[N_FACES];
+      double usum = 0;
+      for (int f = 0; f < N_FACES; ++f) {
+        u[f] = sin(0.61 * f);
+        usum += fabs(u[f]) * farea[f];
+      }
+      double *du = (double *)dev_copy(u, sizeof u), *dL = NULL, *dL2 = NULL;
+      HIP_CHECK(hipMalloc((void **)&dL, sizeof(double)));
+      HIP_CHECK(hipMalloc((void **)&dL2, sizeof(double)));
+      const size_t ni = (size_t)N_CELLS * K_ANG * (dtype == RT_F64 ? sizeof(double) : sizeof(float));
+      void *ds1 = NULL, *ds2 = NULL;
+      HIP_CHECK(hipMalloc(&ds1, ni));
+      HIP_CHECK(hipMalloc(&ds2, ni));
+      HIP_CHECK(hipMemset(ds1, 0, ni));
+      HIP_CHECK(hipMemset(ds2, 0, ni));
+      void *dF = dev_intensities(I, dtype); /* the non-uniform field of check 3a */
+      RT_CHECK(rt_flux_loss(mesh, &prm, &ang, dF, du, dL, ds1, NULL));
+      RT_CHECK(rt_flux_loss_noalloc(mesh, &prm, &ang, dF, du, dL2, ds2, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      double L1, L2;
+      HIP_CHECK(hipMemcpy(&L1, dL, sizeof L1, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(&L2, dL2, sizeof L2, hipMemcpyDeviceToHost));
+      char *h1 = (char *)malloc(ni), *h2 = (char *)malloc(ni);
+      HIP_CHECK(hipMemcpy(h1, ds1, ni, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(h2, ds2, ni, hipMemcpyDeviceToHost));
+      snprintf(what, sizeof what, "%s flux loss without allocation equals rt_flux_loss bit for bit: loss", form);
+      expect(memcmp(&L1, &L2, sizeof L1) == 0 && L1 != 0.0, what, fabs(L1 - L2), 0.0);
+      snprintf(what, sizeof what, "%s flux loss without allocation: seed dL/dI bit for bit", form);
+      expect(memcmp(h1, h2, ni) == 0, what, (double)memcmp(h1, h2, ni), 0.0);
+      free(h1);
+      free(h2);
+      HIP_CHECK(hipFree(dF));
+      RT_CHECK(rt_flux_loss(mesh, &prm, &ang, dI, du, dL, NULL, NULL)); /* dI holds the equilibrium field */
+      HIP_CHECK(hipMemcpy(&L1, dL, sizeof L1, hipMemcpyDeviceToHost));
+      const double scale = usum * 4.0 * PI * c_light * Bs;
+      snprintf(what, sizeof what, "%s flux loss of an isotropic field: |L| / (sum |u| A 4 pi c B)", form);
+      expect(fabs(L1) / scale < 1e-14, what, fabs(L1) / scale, 1e-14);
+      HIP_CHECK(hipFree(du));
+      HIP_CHECK(hipFree(dL));
+      HIP_CHECK(hipFree(dL2));
+      HIP_CHECK(hipFree(ds1));
+      HIP_CHECK(hipFree(ds2));
+
+      /* 6d. the limited gradient of a linear field is exact away from the periodic wrap */
+      static double lin[N_CELLS * K_ANG], gr[N_CELLS * 3 * K_ANG];
+      for (int i = 0; i < N_CELLS; ++i)
+        for (int k = 0; k < K_ANG; ++k)
+          lin[i * K_ANG + k] = 3.0 + (0.5 + 0.1 * k) * gen[i][0] - 0.3 * gen[i][1] + 0.2 * k * gen[i][2];
+      void *dlin = dev_intensities(lin, dtype);
+      void *dgr = NULL;
+      const size_t ng = (size_t)N_CELLS * 3 * K_ANG * (dtype == RT_F64 ? sizeof(double) : sizeof(float));
+      HIP_CHECK(hipMalloc(&dgr, ng));
+      RT_CHECK(rt_gradient(mesh, &prm, &ang, dlin, dgr, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      if (dtype == RT_F64) {
+        HIP_CHECK(hipMemcpy(gr, dgr, ng, hipMemcpyDeviceToHost));
+      } else {
+        float *gf = (float *)malloc(ng);
+        HIP_CHECK(hipMemcpy(gf, dgr, ng, hipMemcpyDeviceToHost));
+        for (int i = 0; i < N_CELLS * 3 * K_ANG; ++i) gr[i] = gf[i];
+        free(gf);
+      }
+      double eGr = 0;
+      for (int z = 1; z < N_SIDE - 1; ++z)
+        for (int y = 1; y < N_SIDE - 1; ++y)
+          for (int x = 1; x < N_SIDE - 1; ++x) {
+            const int i = x + N_SIDE * (y + N_SIDE * z);
+            for (int k = 0; k < K_ANG; ++k) {
+              const double ex[3] = {0.5 + 0.1 * k, -0.3, 0.2 * k};
+              for (int a = 0; a < 3; ++a)
+                eGr = fmax(eGr, fabs(gr[(i * 3 + a) * K_ANG + k] - ex[a]) / 2.0);
+            }
+          }
+      const double bGr = dtype == RT_F64 ? 1e-12 : 1e-4;
+      snprintf(what, sizeof what, "%s limited gradient of a linear field (interior cells): max |error| / max |grad|",
+               form);
+      expect(eGr < bGr, what, eGr, bGr);
+      HIP_CHECK(hipFree(dlin));
+      HIP_CHECK(hipFree(dgr));
     }
 
     HIP_CHECK(hipFree(dI));

@@ -8,8 +8,10 @@ T^n); fused steps away from equilibrium keep the energy and momentum totals that
 rt_diagnostics reports (section 2.3.1); first-order and PLM-VL2 transport conserve every
 angle's total (first order keeps I >= 0, PLM keeps a uniform field uniform; section 2.2);
 rt_moments gives E_r = 4 pi B, F_r = 0, P_r = E_r/3 for an isotropic field (section 2.1);
-and at zero opacity rt_step_adjoint is the transpose of the step.  The program prints one
-line per check and "ok" last."""
+at zero opacity rt_step_adjoint is the transpose of the step; the multigroup and kappa(T)
+steps keep equilibrium; rt_flux_loss_noalloc reproduces rt_flux_loss bit for bit and an
+isotropic field's loss vanishes; rt_gradient is exact for a linear field away from the
+periodic wrap.  The program prints one line per check and "ok" last."""
 import importlib.util
 import os
 import subprocess
@@ -39,4 +41,4 @@ def test_c_program_runs_the_step_on_the_gpu():
     assert r.returncode == 0, r.stdout + r.stderr
     lines = r.stdout.strip().splitlines()
     assert lines[-1] == "ok"
-    assert sum(line.startswith("pass ") for line in lines) == 29, r.stdout
+    assert sum(line.startswith("pass ") for line in lines) == 49, r.stdout
