@@ -79,6 +79,10 @@ static void *dev_intensities(const double *I, int dtype) {
   return d;
 }
 
+static size_t ni_bytes(int dtype) {
+  return (size_t)N_CELLS * K_ANG * (dtype == RT_F64 ? sizeof(double) : sizeof(float));
+}
+
 static void host_intensities(double *I, const void *d, int dtype) {
   const size_t n = (size_t)N_CELLS * K_ANG;
   if (dtype == RT_F64) {
@@ -126,6 +130,29 @@ int main(void) {
                           &vel[0][0],
                           &fcell[0][0], &fshift[0][0], farea, &fnorm[0][0], &fcen[0][0], box, NULL));
   const double c_red = 10.0, c_light = 100.0;
+  {
+    int64_t nc = 0, nf = 0, nh = 0;
+    int32_t km = 0, fl = 0;
+    RT_CHECK(rt_mesh_info(mesh, &nc, &nf, &nh, &km, &fl));
+    expect(nc == N_CELLS && nf == N_FACES && nh == 2 * N_FACES && km == K_ANG &&
+               fl == (RT_MESH_PLM | RT_MESH_ADJOINT),
+           "rt_mesh_info returns the uploaded sizes (two half-faces per face)", (double)nh, 2.0 * N_FACES);
+    double *dws = NULL, *dD = NULL;
+    static double ws[N_FACES], D[N_CELLS];
+    HIP_CHECK(hipMalloc((void **)&dws, sizeof ws));
+    HIP_CHECK(hipMalloc((void **)&dD, sizeof D));
+    RT_CHECK(rt_mesh_geometry(mesh, dws, dD, NULL));
+    HIP_CHECK(hipDeviceSynchronize());
+    HIP_CHECK(hipMemcpy(ws, dws, sizeof ws, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(D, dD, sizeof D, hipMemcpyDeviceToHost));
+    double ew = 0, eD = 0;
+    for (int f = 0; f < N_FACES; ++f) ew = fmax(ew, fabs(ws[f] - vel[0][f % 3])); /* face f normal to axis f % 3 */
+    for (int i = 0; i < N_CELLS; ++i) eD = fmax(eD, fabs(D[i]));
+    expect(ew < 1e-15, "face normal speeds of a uniform drift (eq. 9): max |w.n - w_axis|", ew, 1e-15);
+    expect(eD < 1e-15, "volume rates of a uniform drift: max |D|", eD, 1e-15);
+    HIP_CHECK(hipFree(dws));
+    HIP_CHECK(hipFree(dD));
+  }
 
   /* eight diagonal directions, each antipode K/2 further on, equal weights */
   double dir[K_ANG][3], w[K_ANG];
@@ -391,6 +418,46 @@ int main(void) {
       const double bD = dtype == RT_F64 ? 1e-14 : 1e-6;
       snprintf(what, sizeof what, "%s adjoint at zero opacity: |<T x, y> - <x, T' y>| / (|T x| |y|)", form);
       expect(eD < bD, what, eD, bD);
+      /* the run adjoint over three taped steps (arrays of device pointers, as from C) */
+      enum { NS = 3 };
+      void *outs[NS];
+      double *tapes[NS];
+      void *cur = dI; /* holds x */
+      HIP_CHECK(hipMemcpy(dvol, vol, sizeof vol, hipMemcpyHostToDevice));
+      for (int n = 0; n < NS; ++n) {
+        HIP_CHECK(hipMalloc(&outs[n], ni_bytes(dtype)));
+        HIP_CHECK(hipMalloc((void **)&tapes[n], sizeof(double) * N_CELLS * RT_SRC_TAPE));
+        RT_CHECK(rt_step_taped(mesh, &prm, &ang, cur, outs[n], NULL, dvol, drho, dmom, detot, zero, zero, zero, NULL,
+                               tapes[n], NULL));
+        cur = outs[n];
+      }
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Tx, outs[NS - 1], dtype);
+      {
+        void *ycopy = dev_intensities(y, dtype); /* y is already in the stored precision */
+        HIP_CHECK(hipMemcpy(dlam, ycopy, ni_bytes(dtype), hipMemcpyDeviceToDevice));
+        HIP_CHECK(hipFree(ycopy));
+      }
+      HIP_CHECK(hipMemset(dlE, 0, sizeof vol));
+      HIP_CHECK(hipMemset(dlM, 0, sizeof mom));
+      RT_CHECK(rt_step_adjoint_run(mesh, &prm, &ang, NS, (const void *const *)outs, (const double *const *)tapes,
+                                   drho, zero, zero, zero, dlam, dlE, dlM, NULL, NULL, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      host_intensities(Ty, dlam, dtype);
+      lhs = rhs = nx = 0;
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) {
+        lhs += Tx[i] * y[i];
+        rhs += x[i] * Ty[i];
+        nx += Tx[i] * Tx[i];
+      }
+      const double eR = fabs(lhs - rhs) / sqrt(nx * ny);
+      snprintf(what, sizeof what, "%s run adjoint of 3 taped steps at zero opacity: |<T^3 x, y> - <x, T^3' y>| / norms",
+               form);
+      expect(eR < bD, what, eR, bD);
+      for (int n = 0; n < NS; ++n) {
+        HIP_CHECK(hipFree(outs[n]));
+        HIP_CHECK(hipFree(tapes[n]));
+      }
       HIP_CHECK(hipFree(dlam));
       HIP_CHECK(hipFree(dlE));
       HIP_CHECK(hipFree(dlM));
