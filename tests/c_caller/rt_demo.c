@@ -18,7 +18,13 @@
  *      must apply its transpose: <T x, y> = <x, T' y> to rounding;
  *   6. the multigroup and kappa(T) steps keep equilibrium too; rt_flux_loss_noalloc gives
  *      rt_flux_loss's loss and seed bit for bit, and an isotropic field's loss is zero; the
- *      limited gradient of a linear field is exact away from the periodic wrap.
+ *      limited gradient of a linear field is exact away from the periodic wrap;
+ *   7. marked cells (sections 2.4-2.5): fully relaxed boundary cells hold S in their
+ *      directions of interest and 0 elsewhere and lose their momentum with its kinetic
+ *      energy; emitters follow their implicit closed form; other cells are untouched;
+ *   8. the grey and multigroup sources alone keep a comoving equilibrium on moving gas
+ *      (I_k = B / Gamma_k^4).
+ * Every function that rtmm.h declares is called.
  * Device memory comes from HIP's runtime API.  Prints one line per check and "ok" last;
  * exit status 0 only if every check passes.
  */
@@ -125,6 +131,7 @@ int main(void) {
           farea[f] = h * h;
         }
       }
+  expect(rt_version() == 1, "rt_version", (double)rt_version(), 1.0);
   rt_mesh *mesh = NULL;
   RT_CHECK(rt_mesh_upload(&mesh, N_CELLS, N_FACES, K_ANG, RT_MESH_PLM | RT_MESH_ADJOINT, &gen[0][0], &gen[0][0], vol,
                           &vel[0][0],
@@ -637,6 +644,158 @@ int main(void) {
       expect(eGr < bGr, what, eGr, bGr);
       HIP_CHECK(hipFree(dlin));
       HIP_CHECK(hipFree(dgr));
+    }
+
+    /* 7. marked cells: boundary cells relaxed fully (tau <= dt) and emitters (sections 2.4-2.5) */
+    {
+      enum { NM = 5 };
+      const int32_t mcell[NM] = {0, 5, 17, 30, 31};
+      const int32_t mkind[NM] = {RT_CELL_BOUNDARY, RT_CELL_BOUNDARY, RT_CELL_BOUNDARY, RT_CELL_EMITTER,
+                                 RT_CELL_EMITTER};
+      const double mT[NM] = {2.0, 2.0, 2.0, 1.5, 1.5};
+      double mdir[NM][3], mcos[NM];
+      for (int m = 0; m < NM; ++m) {
+        const double sg = mkind[m] == RT_CELL_BOUNDARY ? 1.0 : -1.0;
+        for (int b = 0; b < 3; ++b) mdir[m][b] = sg / sqrt(3.0);
+        mcos[m] = mkind[m] == RT_CELL_BOUNDARY ? 0.3 : -0.2; /* four of the eight directions each */
+      }
+      rt_marked *set = NULL;
+      RT_CHECK(rt_marked_upload(&set, N_CELLS, NM, mcell, mkind, mT, &mdir[0][0], mcos, 0.5 * dt, NULL));
+      for (int i = 0; i < N_CELLS * K_ANG; ++i) Ih[i] = 0.7 * B;
+      HIP_CHECK(hipFree(dI));
+      dI = dev_intensities(Ih, dtype);
+      host_intensities(Ih, dI, dtype); /* as stored */
+      static double mm[N_CELLS][3], em[N_CELLS];
+      for (int i = 0; i < N_CELLS; ++i) {
+        for (int a = 0; a < 3; ++a) mm[i][a] = (i == 0 || i == 5 || i == 17) ? rho[i] * (0.2 + 0.1 * a) : 0.0;
+        em[i] = etot[i] + 0.5 * (mm[i][0] * mm[i][0] + mm[i][1] * mm[i][1] + mm[i][2] * mm[i][2]) / rho[i];
+      }
+      HIP_CHECK(hipMemcpy(dmom, mm, sizeof mm, hipMemcpyHostToDevice));
+      HIP_CHECK(hipMemcpy(detot, em, sizeof em, hipMemcpyHostToDevice));
+      RT_CHECK(rt_marked_apply(mesh, &prm, &ang, set, dI, drho, dmom, detot, dk, NULL));
+      HIP_CHECK(hipDeviceSynchronize());
+      static double Im[N_CELLS * K_ANG], m3[N_CELLS][3], e3[N_CELLS];
+      host_intensities(Im, dI, dtype);
+      HIP_CHECK(hipMemcpy(m3, dmom, sizeof m3, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(e3, detot, sizeof e3, hipMemcpyDeviceToHost));
+      double eBnd = 0, eGas = 0, eEm = 0, eRest = 0;
+      for (int m = 0; m < NM; ++m) {
+        const int i = mcell[m];
+        const double S = a_rad * pow(mT[m], 4) / (4.0 * PI);
+        for (int k = 0; k < K_ANG; ++k) {
+          const double dot = dir[k][0] * mdir[m][0] + dir[k][1] * mdir[m][1] + dir[k][2] * mdir[m][2];
+          const int on = dot >= mcos[m];
+          const double got = Im[i * K_ANG + k], was = Ih[i * K_ANG + k];
+          if (mkind[m] == RT_CELL_BOUNDARY) {
+            eBnd = fmax(eBnd, fabs(got - (on ? S : 0.0)) / S);
+          } else {
+            const double x = dt * c_red * rho[i] * kap[i]; /* gas at rest: Gamma = 1 */
+            const double want = on ? (was + x * S) / (1.0 + x) : was;
+            eEm = fmax(eEm, fabs(got - want) / want);
+          }
+        }
+        if (mkind[m] == RT_CELL_BOUNDARY) {
+          const double ke = 0.5 * (mm[i][0] * mm[i][0] + mm[i][1] * mm[i][1] + mm[i][2] * mm[i][2]) / rho[i];
+          for (int a = 0; a < 3; ++a) eGas = fmax(eGas, fabs(m3[i][a]) / fabs(mm[i][0]));
+          eGas = fmax(eGas, fabs(e3[i] - (em[i] - ke)) / em[i]);
+        } else {
+          eGas = fmax(eGas, fabs(e3[i] - em[i]) / em[i]);
+        }
+      }
+      for (int i = 0; i < N_CELLS; ++i) { /* cells not marked are untouched */
+        int marked = 0;
+        for (int m = 0; m < NM; ++m) marked |= mcell[m] == i;
+        if (marked) continue;
+        for (int k = 0; k < K_ANG; ++k) eRest = fmax(eRest, fabs(Im[i * K_ANG + k] - Ih[i * K_ANG + k]));
+        eRest = fmax(eRest, fabs(e3[i] - em[i]));
+      }
+      const double bM = dtype == RT_F64 ? 1e-14 : 1e-6;
+      snprintf(what, sizeof what, "%s boundary cells (tau <= dt): I = S in the directions of interest, else 0", form);
+      expect(eBnd < bM, what, eBnd, bM);
+      snprintf(what, sizeof what, "%s marked cells' gas: boundary rho v -> 0 with its kinetic energy; emitters keep it",
+               form);
+      expect(eGas < 1e-14, what, eGas, 1e-14);
+      snprintf(what, sizeof what, "%s emitter cells: I' = (I + x S) / (1 + x) in the directions of interest", form);
+      expect(eEm < bM, what, eEm, bM);
+      snprintf(what, sizeof what, "%s cells not marked are untouched: max |change|", form);
+      expect(eRest == 0.0, what, eRest, 0.0);
+      RT_CHECK(rt_marked_free(set));
+    }
+
+    /* 8. the grey and multigroup sources alone, on moving gas at comoving equilibrium:
+          I_k = B / Gamma_k^4, Gamma_k = gamma (1 - v.n_k / c) (section 2.3) */
+    {
+      static double vg[N_CELLS][3], mv[N_CELLS][3], ev[N_CELLS], Ieq[N_CELLS * K_ANG];
+      for (int i = 0; i < N_CELLS; ++i) {
+        for (int a = 0; a < 3; ++a) vg[i][a] = 0.05 * c_light * sin(0.9 * i + 2.1 * a) / sqrt(3.0);
+        const double v2 = vg[i][0] * vg[i][0] + vg[i][1] * vg[i][1] + vg[i][2] * vg[i][2];
+        const double gam = 1.0 / sqrt(1.0 - v2 / (c_light * c_light));
+        for (int a = 0; a < 3; ++a) mv[i][a] = rho[i] * vg[i][a];
+        ev[i] = etot[i] + 0.5 * rho[i] * v2;
+        for (int k = 0; k < K_ANG; ++k) {
+          const double vn = vg[i][0] * dir[k][0] + vg[i][1] * dir[k][1] + vg[i][2] * dir[k][2];
+          const double Gk = gam * (1.0 - vn / c_light);
+          Ieq[i * K_ANG + k] = B / (Gk * Gk * Gk * Gk);
+        }
+      }
+      const double bI8 = dtype == RT_F64 ? 1e-13 : 5e-6, bG8 = dtype == RT_F64 ? 1e-12 : 1e-4;
+      for (int pass = 0; pass < 2; ++pass) { /* 0: grey source, 1: multigroup (2 groups) */
+        const int G = pass == 0 ? 1 : 2;
+        void *dS = NULL;
+        const size_t one = ni_bytes(dtype);
+        HIP_CHECK(hipMalloc(&dS, G * one));
+        for (int j = 0; j < G; ++j) {
+          void *part = dev_intensities(Ieq, dtype);
+          HIP_CHECK(hipMemcpy((char *)dS + j * one, part, one, hipMemcpyDeviceToDevice));
+          HIP_CHECK(hipFree(part));
+        }
+        static double Ist[N_CELLS * K_ANG];
+        host_intensities(Ist, dS, dtype); /* as stored */
+        HIP_CHECK(hipMemcpy(dmom, mv, sizeof mv, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(detot, ev, sizeof ev, hipMemcpyHostToDevice));
+        if (pass == 0) {
+          RT_CHECK(rt_source_implicit(mesh, &prm, &ang, dS, drho, dmom, detot, dk, dk, dks, dT, NULL));
+        } else {
+          const double wg2[2] = {0.4, 0.6};
+          static double k2[2 * N_CELLS], s2[2 * N_CELLS];
+          for (int i = 0; i < N_CELLS; ++i) {
+            k2[i] = kap[i];
+            k2[N_CELLS + i] = 2.5 * kap[i];
+            s2[i] = ks[i];
+            s2[N_CELLS + i] = 0.1;
+          }
+          double *dw2 = (double *)dev_copy(wg2, sizeof wg2), *dk2 = (double *)dev_copy(k2, sizeof k2);
+          double *ds2 = (double *)dev_copy(s2, sizeof s2);
+          RT_CHECK(rt_source_implicit_mg(mesh, &prm, &ang, 2, dw2, dS, drho, dmom, detot, dk2, dk2, ds2, dT, NULL));
+          HIP_CHECK(hipDeviceSynchronize());
+          HIP_CHECK(hipFree(dw2));
+          HIP_CHECK(hipFree(dk2));
+          HIP_CHECK(hipFree(ds2));
+        }
+        HIP_CHECK(hipDeviceSynchronize());
+        double eI8 = 0, eG8 = 0;
+        for (int j = 0; j < G; ++j) {
+          host_intensities(Ih, (char *)dS + j * one, dtype);
+          for (int i = 0; i < N_CELLS * K_ANG; ++i) eI8 = fmax(eI8, fabs(Ih[i] - Ist[i]) / Ist[i]);
+        }
+        static double m8[N_CELLS][3], e8[N_CELLS], T8[N_CELLS];
+        HIP_CHECK(hipMemcpy(m8, dmom, sizeof m8, hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpy(e8, detot, sizeof e8, hipMemcpyDeviceToHost));
+        HIP_CHECK(hipMemcpy(T8, dT, sizeof T8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < N_CELLS; ++i) {
+          const double mn = sqrt(mv[i][0] * mv[i][0] + mv[i][1] * mv[i][1] + mv[i][2] * mv[i][2]) + 4.0 * PI * B / c_red;
+          for (int a = 0; a < 3; ++a) eG8 = fmax(eG8, fabs(m8[i][a] - mv[i][a]) / mn);
+          eG8 = fmax(eG8, fabs(e8[i] - ev[i]) / ev[i]);
+          eG8 = fmax(eG8, fabs(T8[i] - T0) / T0);
+        }
+        snprintf(what, sizeof what, "%s %s source alone, moving gas at comoving equilibrium: max |I' - I| / I", form,
+                 pass == 0 ? "grey" : "multigroup");
+        expect(eI8 < bI8, what, eI8, bI8);
+        snprintf(what, sizeof what, "%s %s source alone: T, E_g and rho v kept (max relative change)", form,
+                 pass == 0 ? "grey" : "multigroup");
+        expect(eG8 < bG8, what, eG8, bG8);
+        HIP_CHECK(hipFree(dS));
+      }
     }
 
     HIP_CHECK(hipFree(dI));

@@ -82,3 +82,15 @@ def test_c_program_links_and_calls_the_host_paths(tmp_path):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
+
+
+def test_c_caller_calls_every_declared_function():
+    """The C program that a GPU test runs (tests/c_caller/rt_demo.c) calls every function rtmm.h
+    declares, so the whole ABI is exercised from C without the Python binding."""
+    import re
+    src = open(os.path.join(INC, "rtmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(rt_[a-z0-9_]+)\s*\(", src)))
+    prog = open(os.path.join(ROOT, "tests", "c_caller", "rt_demo.c")).read()
+    missing = [d for d in declared if not re.search(r"\b" + d + r"\s*\(", prog)]
+    assert len(declared) >= 20 and not missing, missing
