@@ -272,6 +272,42 @@ def test_adjoint_32c_48a_full_size_matches_finite_differences():
         assert abs(fd - gI[c, k]) <= 1e-6 * abs(gI[c, k]) + floor / (2 * e), ("I0", c, k, fd, gI[c, k])
 
 
+
+@pytest.mark.timeout(900)
+def test_fwd_adj_96c_80a_matches_oracle():
+    """Full size and length of the checkpointed workload against the oracle's reverse mode:
+    96^3 cells, 80 angles (antipodes side by side, as the bench times it), 40 steps,
+    checkpoints every 8.  One oracle run (loss and both gradients, FP64); the GPU's FP64 form
+    within 1e-12 (loss) and 1e-10 (gradients, normwise; element-wise 1e-8 over the entries
+    above 1e-8 of the largest), its FP32-transport form within 1e-5 (loss, dL/dI0) and 1e-4
+    (dL/dkappa)."""
+    p = inp.with_angle_order(inp.make_problem(4), inp.adjacent_pair_order(80))
+    st = p.state
+    u = inp.loss_face_weights(p.mesh, p.seeds["omega"])
+    print("oracle reverse mode, 96^3 x 80 x 40 ...", flush=True)
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    Lo, gIo, gko = orc.adjoint(om, p.dirs, p.weights, p.phys, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot),
+                               st.rho, st.kP, st.ks, p.steps, u)
+    del om
+    fw = _d(u)
+    for dtype in (rt.F64, rt.F32):
+        system, x = _system(p, dtype)
+        L, gI, gk, _, _ = _grads(system, x, fw, p.steps, 8)
+        gI, gk = gI.double().cpu().numpy(), gk.cpu().numpy()
+        system.mesh.free()
+        del system, x
+        torch.cuda.empty_cache()
+        err = {"L": abs(L - Lo) / abs(Lo), "gI": rel_err(gI, gIo), "gk": rel_err(gk, gko),
+               "gI_elem": elem_err(gI, gIo, 1e-8 * np.abs(gIo).max()),
+               "gk_elem": elem_err(gk, gko, 1e-8 * np.abs(gko).max())}
+        print(f"fwd+adj 96^3 x 80 x 40, {'FP64' if dtype == rt.F64 else 'FP32'} vs oracle:",
+              {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+        if dtype == rt.F64:
+            assert err["L"] < 1e-12 and err["gI"] < 1e-10 and err["gk"] < 1e-10, err
+            assert err["gI_elem"] < 1e-8 and err["gk_elem"] < 1e-8, err
+        else:
+            assert err["L"] < 1e-5 and err["gI"] < 1e-5 and err["gk"] < 1e-4, err
+
 def test_fwd_adj_96c_80a_f32_against_f64():
     """Full size of the checkpointed workload: 96^3 cells, 80 angles, 40 steps, checkpoints every 8."""
     p = inp.make_problem(4)
