@@ -298,6 +298,58 @@ def test_throughput_128c_80a_ten_steps(dtype, order, throughput_problem):
 
 
 
+
+@pytest.mark.timeout(900)
+def test_throughput_128c_80a_bench_length_matches_oracle(throughput_problem):
+    """The bench's whole run: 128^3 cells x 80 angles, 50 fused steps from the recipe's state,
+    antipodes side by side (the launches the bench times), both forms against one 50-step
+    oracle run, every cell and angle, normwise and element-wise."""
+    p, _, _ = throughput_problem
+    steps = inp.CONFIGS[3].steps  # the bench's length (the fixture's problem holds 10)
+    assert steps == 50
+    perm = inp.adjacent_pair_order(80)
+    st = p.state
+    print("oracle, 128^3 x 80 x 50 ...", flush=True)
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    so, To = orc.run(om, p.dirs, p.weights, p.phys, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot), st.rho, st.kP,
+                     st.kJ, st.ks, steps, "upwind1")
+    del om
+    Io = np.ascontiguousarray(so.I[:, perm])
+    q = inp.with_angle_order(p, perm)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    mesh = rt.Mesh.from_inputs(q.mesh, q.state.mesh_vel, k_max=80)
+    ang = rt.AngleSet(q.dirs, q.weights)
+    for dtype in (rt.F64, rt.F32):
+        qs = q.state
+        prm = rt.make_params(q.phys.c_red, q.phys.c_light, q.phys.a_rad, q.phys.cv, q.dt, dtype)
+        I = d(qs.I).to(rt.torch_dtype(dtype)).contiguous()
+        I2 = torch.empty_like(I)
+        vol, mom, etot = d(qs.vol), d(qs.mom), d(qs.etot)
+        T = torch.zeros(qs.rho.shape, dtype=torch.float64, device="cuda")
+        rho, kP, kJ, ks = d(qs.rho), d(qs.kP), d(qs.kJ), d(qs.ks)
+        for _ in range(steps):
+            rt.step(mesh, prm, ang, I, I2, vol, rho, mom, etot, kP, kJ, ks, T)
+            I, I2 = I2, I
+        torch.cuda.synchronize()
+        Ih = I.double().cpu().numpy()
+        del I, I2
+        Th, eh, mh = T.cpu().numpy(), etot.cpu().numpy(), mom.cpu().numpy()
+        err = {"I": rel_err(Ih, Io), "I_elem": elem_err(Ih, Io), "T": rel_err(Th, To), "T_elem": elem_err(Th, To),
+               "etot": rel_err(eh, so.etot), "etot_elem": elem_err(eh, so.etot), "mom": rel_err(mh, so.mom),
+               "mom_cell": vec_err(mh, so.mom, np.linalg.norm(so.mom, axis=1)), "vol": rel_err(vol.cpu().numpy(), so.vol)}
+        print(f"throughput 128^3 x 80, 50 steps, {'FP64' if dtype == rt.F64 else 'FP32'}:",
+              {k: f"{v:.2e}" for k, v in err.items()}, flush=True)
+        assert err["I"] < TOL[dtype] and err["vol"] < 1e-14, err
+        if dtype == rt.F64:
+            assert err["T"] < 1e-12 and err["etot"] < 1e-12 and err["mom"] < 1e-12, err
+            assert err["I_elem"] < 1e-11 and err["T_elem"] < 1e-12 and err["etot_elem"] < 1e-12, err
+            assert err["mom_cell"] < 1e-11, err
+        else:
+            assert err["I_elem"] < 1e-5, err
+            assert err["T"] < 1e-6 * steps and err["etot"] < 1e-6 * steps and err["mom"] < 1e-6 * steps, err
+    ang.free()
+    mesh.free()
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 @pytest.mark.parametrize("fast", [False, True])
