@@ -350,6 +350,105 @@ def test_throughput_128c_80a_bench_length_matches_oracle(throughput_problem):
     ang.free()
     mesh.free()
 
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_extension_rows_at_full_size_match_oracle(dtype, throughput_problem):
+    """The extension rows as the bench runs them on the throughput mesh (128^3 cells x 80
+    angles, antipodes K/2 apart), each against the oracle at full size: one multigroup step
+    (4 groups, opacities scaled 0.3 to 10, weights 0.1 to 0.4), one step with Kramers-like
+    opacities (exponent -3.5 about T_ref = 1), the boundary and emitter cells (1% of the cells,
+    half of each kind) applied once, and the angle moments.  FP64 within 1e-12 (element-wise
+    1e-11 on intensities); the FP32 form within 1e-5 on intensities and 1e-6 on T and E_g."""
+    p, _, _ = throughput_problem
+    st, ph = p.state, p.phys
+    N, K = st.I.shape
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    td = rt.torch_dtype(dtype)
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    assert ang.layout == rt.ANGLES_ANTIPODAL
+    prm = rt.make_params(ph.c_red, ph.c_light, ph.a_rad, ph.cv, p.dt, dtype)
+    om = orc.OracleMesh(p.mesh, st.mesh_vel)
+    tolI, tolG = (1e-12, 1e-12) if dtype == rt.F64 else (1e-5, 1e-6)
+    errs = {}
+
+    # multigroup: one step of 4 transports and the multigroup source
+    G = 4
+    Wg = np.array([0.1, 0.2, 0.3, 0.4])
+    scale = np.array([0.3, 1.0, 3.0, 10.0])[:, None]
+    kPg, kJg, ksg = scale * st.kP[None, :], scale * st.kJ[None, :], np.tile(st.ks, (G, 1))
+    Ig = d(st.I).to(td)[None].repeat(G, 1, 1).contiguous()
+    Ig2 = torch.empty_like(Ig)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    T = torch.zeros(N, dtype=torch.float64, device="cuda")
+    rt.step_mg(mesh, prm, ang, d(Wg), Ig, Ig2, vol, d(st.rho), mom, etot, d(kPg), d(kJg), d(ksg), T)
+    torch.cuda.synchronize()
+    tr = [orc.step(om, p.dirs, p.weights, ph, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot), st.rho, kPg[j],
+                   kJg[j], ksg[j], with_source=False)[0] for j in range(G)]
+    Io, mo, eo, To = orc.source_mg(p.dirs, p.weights, Wg, ph, p.dt, np.stack([t.I for t in tr]), st.rho, st.mom,
+                                   st.etot, kPg, kJg, ksg)
+    del tr
+    Ih = Ig2.double().cpu().numpy()
+    errs["mg"] = {"I": rel_err(Ih, Io), "I_elem": elem_err(Ih, Io), "T": rel_err(T.cpu().numpy(), To),
+                  "etot": rel_err(etot.cpu().numpy(), eo)}
+    del Ig, Ig2, Ih, Io
+
+    # kappa(T): one step (transport, then the source with Kramers-like opacities)
+    law = (1.0, -3.5, -3.5)
+    I = d(st.I).to(td).contiguous()
+    I2 = torch.empty_like(I)
+    vol, mom, etot = d(st.vol), d(st.mom), d(st.etot)
+    rt.step_kT(mesh, prm, ang, I, I2, vol, d(st.rho), mom, etot, d(st.kP), d(st.kJ), d(st.ks), *law, T)
+    torch.cuda.synchronize()
+    s, _ = orc.step(om, p.dirs, p.weights, ph, p.dt, orc.OState(st.I, st.vol, st.mom, st.etot), st.rho, st.kP,
+                    st.kJ, st.ks, with_source=False)
+    Io, mo, eo, To = orc.source_kT(p.dirs, p.weights, ph, p.dt, s.I, st.rho, s.mom, s.etot, st.kP, st.kJ, st.ks,
+                                   *law)
+    Ih = I2.double().cpu().numpy()
+    errs["kT"] = {"I": rel_err(Ih, Io), "I_elem": elem_err(Ih, Io), "T": rel_err(T.cpu().numpy(), To),
+                  "etot": rel_err(etot.cpu().numpy(), eo)}
+
+    # boundary and emitter cells on the state after that step, then the angle moments
+    rng = np.random.default_rng(2002)
+    M = N // 100
+    cells = rng.choice(N, M, replace=False)
+    kinds = np.where(np.arange(M) % 2 == 0, rt.CELL_BOUNDARY, rt.CELL_EMITTER)
+    dirs = rng.normal(size=(M, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    T_eff, cos_open, tau = rng.uniform(0.5, 2.0, M), np.full(M, 0.8), 4.0 * p.dt
+    mk = rt.MarkedCells(N, cells, kinds, T_eff, dirs, cos_open, tau)
+    Istart = Ih.copy()  # the stored (for FP32, rounded) field the marked cells start from
+    mstart, estart = mom.cpu().numpy(), etot.cpu().numpy()
+    rt.marked_apply(mesh, prm, ang, mk, I2, d(st.rho), mom, etot, d(st.kP))
+    torch.cuda.synchronize()
+    mk.free()
+    so = orc.marked_cells(p.dirs, ph, p.dt, orc.OState(Istart, st.vol, mstart, estart), st.rho, st.kP, cells,
+                          kinds, T_eff, dirs, cos_open, tau)
+    Ih = I2.double().cpu().numpy()
+    errs["marked"] = {"I": rel_err(Ih, so.I), "I_elem": elem_err(Ih[cells], so.I[cells], 1e-30),
+                      "etot": rel_err(etot.cpu().numpy(), so.etot), "mom": rel_err(mom.cpu().numpy(), so.mom)}
+    mo_d = torch.empty((N, 10), dtype=torch.float64, device="cuda")
+    rt.moments(mesh, prm, ang, I2, mo_d)
+    torch.cuda.synchronize()
+    mref = orc.moments(p.dirs, p.weights, ph.c_light, Ih)
+    errs["moments"] = {"E": rel_err(mo_d[:, 0].cpu().numpy(), mref[:, 0]),
+                       "F": rel_err(mo_d[:, 1:4].cpu().numpy(), mref[:, 1:4]),
+                       "P": rel_err(mo_d[:, 4:].cpu().numpy(), mref[:, 4:])}
+    ang.free()
+    mesh.free()
+    print(f"extension rows 128^3 x 80, {'FP64' if dtype == rt.F64 else 'FP32'} vs oracle:",
+          {r: {k: f"{v:.2e}" for k, v in e.items()} for r, e in errs.items()}, flush=True)
+    for row in ("mg", "kT"):
+        e = errs[row]
+        assert e["I"] < tolI and e["I_elem"] < (1e-11 if dtype == rt.F64 else 1e-5), (row, e)
+        assert e["T"] < tolG and e["etot"] < tolG, (row, e)
+    e = errs["marked"]
+    assert e["I"] < tolI and e["I_elem"] < (1e-11 if dtype == rt.F64 else 1e-5), e
+    assert e["etot"] < 1e-12 and e["mom"] < 1e-12, e
+    # the moments are FP64 sums of the stored values in both forms
+    assert max(errs["moments"].values()) < 1e-13, errs["moments"]
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 @pytest.mark.parametrize("fast", [False, True])
