@@ -167,3 +167,44 @@ def test_angles_check_rejects_bad_claims_on_the_host():
     a = rt._Angles(8, rt.ANGLES_GENERAL, bogus, bogus)
     assert L.rt_angles_check(ctypes.byref(a), None) == rt.RT_OK
     assert L.rt_angles_release(ctypes.byref(a)) == rt.RT_OK
+
+
+def test_last_error_is_per_thread():
+    """rt_last_error() returns the calling thread's own last failure: two threads that fail in
+    different ways, many times over and interleaved, each read back their own message."""
+    import threading
+    L = rt.lib()
+    out = ctypes.c_void_p()
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    gen = np.zeros((2, 3)); com = np.zeros((2, 3)); vol = np.ones(2); w = np.zeros((2, 3))
+    fc_bad = np.array([[0, 2]], dtype=np.int32); fs = np.zeros((1, 3), dtype=np.int8)
+    fa = np.ones(1); fn = np.array([[1.0, 0, 0]]); fcen = np.zeros((1, 3))
+    results = {}
+    barrier = threading.Barrier(2)
+
+    def empty_mesh():
+        msgs = set()
+        barrier.wait()
+        for _ in range(2000):
+            assert L.rt_mesh_upload(ctypes.byref(ctypes.c_void_p()), 0, 0, 8, 0, *([None] * 9), 1.0, None) \
+                == rt.RT_EINVAL
+            msgs.add(L.rt_last_error())
+        results["empty"] = msgs
+
+    def bad_cells():
+        msgs = set()
+        barrier.wait()
+        for _ in range(2000):
+            assert L.rt_mesh_upload(ctypes.byref(ctypes.c_void_p()), 2, 1, 8, 0, p(gen), p(com), p(vol), p(w),
+                                    p(fc_bad), p(fs), p(fa), p(fn), p(fcen), 1.0, None) == rt.RT_EINVAL
+            msgs.add(L.rt_last_error())
+        results["cells"] = msgs
+
+    threads = [threading.Thread(target=empty_mesh), threading.Thread(target=bad_cells)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert len(results["empty"]) == 1 and b"n_cells" in next(iter(results["empty"]))
+    assert len(results["cells"]) == 1 and b"invalid cells" in next(iter(results["cells"]))
+    assert out.value is None
