@@ -726,6 +726,52 @@ def test_equilibrium_is_a_fixed_point_of_the_step_at_full_size(dtype, throughput
         assert err[k] < b, (k, err[k])
 
 
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
+def test_equilibrium_is_a_fixed_point_of_the_plm_step_at_full_size(dtype, plm_problem):
+    """The PLM-VL2 step with its source (both stages) at the PLM workload's size (64^3 x 80,
+    the recipe's moving mesh, cbar = c/10): gas at rest at one T, I = a T^4 / 4 pi, kP = kJ.
+    The limited gradient of a uniform field is zero, so both stages transport it unchanged and
+    both sources keep it (section 2.3): I, T, E_g and rho v stay as they are for 3 steps."""
+    p = plm_problem
+    st = p.state
+    phys = inp.Physics(c_red=10.0, c_light=100.0)
+    N, K = st.I.shape
+    T0 = 1.3
+    B = float(_planck(phys, T0))
+    etot0 = st.rho * phys.cv * T0
+    mesh = rt.Mesh.from_inputs(p.mesh, st.mesh_vel, k_max=K, flags=rt.MESH_PLM)
+    ang = rt.AngleSet(p.dirs, p.weights)
+    prm = rt.make_params(phys.c_red, phys.c_light, phys.a_rad, phys.cv, p.dt, dtype, rt.PLM_VL2)
+    td = rt.torch_dtype(dtype)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    I = torch.full((N, K), B, dtype=td, device="cuda")
+    I2 = torch.empty_like(I)
+    vol, rho, etot = d(st.vol), d(st.rho), d(etot0)
+    mom = torch.zeros((N, 3), dtype=torch.float64, device="cuda")
+    kP, ks = d(st.kP), d(st.ks)
+    T = torch.zeros(N, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        rt.step(mesh, prm, ang, I, I2, vol, rho, mom, etot, kP, kP, ks, T)
+        I, I2 = I2, I
+    torch.cuda.synchronize()
+    amp = np.maximum(1.0, phys.c_light / phys.c_red * 4.0 * np.pi * B / etot0)
+    if dtype == rt.F64:
+        amp = np.ones_like(amp)
+    err = {"I": float((I.double() - B).abs().max()) / B,
+           "T": float(np.max(np.abs(T.cpu().numpy() - T0) / T0 / amp)),
+           "etot": float(np.max(np.abs(etot.cpu().numpy() - etot0) / etot0 / amp)),
+           "mom": float(mom.abs().max()) / (4.0 * np.pi * B / phys.c_red)}
+    print(f"equilibrium 64^3 x 80, 3 PLM steps, {'FP64' if dtype == rt.F64 else 'FP32'}:",
+          {k: f"{v:.2e}" for k, v in err.items()})
+    ang.free()
+    mesh.free()
+    bounds = (dict(I=1e-12, T=1e-12, etot=1e-12, mom=1e-10) if dtype == rt.F64 else
+              dict(I=1e-5, T=1e-6 * 3, etot=1e-6 * 3, mom=1e-4))
+    for k, b in bounds.items():
+        assert err[k] < b, (k, err[k])
+
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dtype", [rt.F64, rt.F32])
 def test_comoving_equilibrium_is_a_fixed_point_of_the_source_at_full_size(dtype, throughput_problem):
