@@ -158,8 +158,10 @@ int rt_angles_release(const rt_angles *angles);
  * volume D_i = sum_faces A (w~.n) (outward positive; the volume update is
  * V^{n+1} = V^n + dt D_i).  k_max bounds K in later calls; flags (RT_MESH_*)
  * select scratch.  Errors: RT_EINVAL (sizes, indices out of range, area <= 0,
- * non-unit normal, a cell whose faces do not close: |sum A n| > 1e-8 V^(2/3)),
- * RT_ENOMEM, RT_EHIP.  On error *out is NULL.  Synchronises `stream`.
+ * non-unit normal, a cell whose faces do not close: |sum A n| > 1e-8 V^(2/3), a
+ * non-finite position, centre of mass, velocity or centroid), RT_ENOMEM, RT_EHIP.
+ * All checks run on the host before any device memory is allocated.  On error *out
+ * is NULL.  Synchronises `stream`.
  */
 int rt_mesh_upload(rt_mesh **out, int64_t n_cells, int64_t n_faces, int32_t k_max, int32_t flags,
                    const double *gen_pos, const double *com, const double *vol, const double *mesh_vel,

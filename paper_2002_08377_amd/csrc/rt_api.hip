@@ -291,6 +291,19 @@ int rt_mesh_upload(rt_mesh **out, int64_t N, int64_t F, int32_t k_max, int32_t f
       !face_centroid)
     return fail(RT_EINVAL, "a mesh array is NULL");
   if (!(box > 0.0) || !isfinite(box)) return fail(RT_EINVAL, "box must be positive");
+  {
+    // positions, centres of mass, velocities and centroids enter the face speeds and the
+    // reconstruction offsets: a non-finite entry would give non-finite intensities later
+    const struct {
+      const double *p;
+      int64_t n;
+      const char *what;
+    } arrs[] = {{gen, 3 * N, "gen_pos"}, {com, 3 * N, "com"}, {mesh_vel, 3 * N, "mesh_vel"},
+                {face_centroid, 3 * F, "face_centroid"}};
+    for (const auto &a : arrs)
+      for (int64_t k = 0; k < a.n; ++k)
+        if (!isfinite(a.p[k])) return fail(RT_EINVAL, "%s has a non-finite entry (index %lld)", a.what, (long long)k);
+  }
   rt_host_mesh hm;
   {
     const std::string why = rt_build_host_mesh(N, F, vol, face_cells, face_shift, face_area, face_normal, hm);

@@ -208,3 +208,90 @@ def test_last_error_is_per_thread():
     assert len(results["empty"]) == 1 and b"n_cells" in next(iter(results["empty"]))
     assert len(results["cells"]) == 1 and b"invalid cells" in next(iter(results["cells"]))
     assert out.value is None
+
+
+def _lattice(n=3):
+    """A valid periodic cubic lattice of n^3 unit-box cells (three faces per cell), host arrays
+    in the argument order of rt_mesh_upload."""
+    h = 1.0 / n
+    N, F = n ** 3, 3 * n ** 3
+    gen = np.zeros((N, 3)); vel = np.zeros((N, 3)); vol = np.full(N, h ** 3)
+    fc = np.zeros((F, 2), dtype=np.int32); fs = np.zeros((F, 3), dtype=np.int8)
+    fa = np.full(F, h * h); fn = np.zeros((F, 3)); fcen = np.zeros((F, 3))
+    for z in range(n):
+        for y in range(n):
+            for x in range(n):
+                c = (x, y, z)
+                i = x + n * (y + n * z)
+                gen[i] = [(v + 0.5) * h for v in c]
+                vel[i] = [0.1, 0.05, 0.0]
+                for a in range(3):
+                    cn = list(c)
+                    cn[a] = (c[a] + 1) % n
+                    f = 3 * i + a
+                    fc[f] = (i, cn[0] + n * (cn[1] + n * cn[2]))
+                    fs[f, a] = 1 if c[a] + 1 == n else 0
+                    fn[f, a] = 1.0
+                    fcen[f] = gen[i]
+                    fcen[f, a] += 0.5 * h
+    return dict(gen=gen, com=gen.copy(), vol=vol, vel=vel, fc=fc, fs=fs, fa=fa, fn=fn, fcen=fcen)
+
+
+def _upload(m, k_max=8, flags=0, box=1.0):
+    L = rt.lib()
+    out = ctypes.c_void_p()
+    p = lambda a: None if a is None else np.ascontiguousarray(a).ctypes.data_as(ctypes.c_void_p)
+    keep = {k: (None if v is None else np.ascontiguousarray(v)) for k, v in m.items()}
+    N, F = keep["gen"].shape[0] if keep["gen"] is not None else 27, keep["fc"].shape[0] if keep["fc"] is not None else 81
+    rc = L.rt_mesh_upload(ctypes.byref(out), N, F, k_max, flags, p(keep["gen"]), p(keep["com"]), p(keep["vol"]),
+                          p(keep["vel"]), p(keep["fc"]), p(keep["fs"]), p(keep["fa"]), p(keep["fn"]), p(keep["fcen"]),
+                          box, None)
+    return rc, out.value, L.rt_last_error()
+
+
+def _mutate(key, index, value):
+    def f(m):
+        m[key] = m[key].copy()
+        m[key][index] = value
+        return m
+    return f
+
+
+MESH_DEFECTS = [
+    ("NaN position", _mutate("gen", (4, 1), np.nan), b"gen_pos"),
+    ("infinite centre of mass", _mutate("com", (7, 0), np.inf), b"com"),
+    ("NaN velocity", _mutate("vel", (0, 2), np.nan), b"mesh_vel"),
+    ("NaN centroid", _mutate("fcen", (10, 0), np.nan), b"face_centroid"),
+    ("zero volume", _mutate("vol", 3, 0.0), b"volume"),
+    ("NaN volume", _mutate("vol", 5, np.nan), b"volume"),
+    ("negative area", _mutate("fa", 2, -1e-3), b"area"),
+    ("NaN area", _mutate("fa", 8, np.nan), b"area"),
+    ("normal not unit", _mutate("fn", (6, 0), 0.9), b"not unit"),
+    ("NaN normal", _mutate("fn", (6, 1), np.nan), b"not unit"),
+    ("cell out of range", _mutate("fc", (9, 1), 27), b"invalid cells"),
+    ("negative cell", _mutate("fc", (9, 0), -1), b"invalid cells"),
+    ("face of a cell with itself", _mutate("fc", (12, 1), 4), b"invalid cells"),
+    ("shift outside {-1,0,1}", _mutate("fs", (5, 0), 2), b"shift"),
+    ("faces that do not close", _mutate("fa", 13, 1.5 / 9.0), b"not closed"),
+    ("a NULL array", lambda m: dict(m, fcen=None), b"NULL"),
+]
+
+
+@pytest.mark.parametrize("name,mutate,why", MESH_DEFECTS, ids=[d[0] for d in MESH_DEFECTS])
+def test_upload_refuses_each_mesh_defect_on_the_host(name, mutate, why):
+    """A valid 3^3 periodic lattice with one defect at a time: every defect is refused with
+    RT_EINVAL before any device memory is touched (this runs without a GPU), *out stays NULL
+    and the message names the defect."""
+    m = _lattice()
+    assert (m["fc"][12] == [4, 5]).all()  # face 12 joins cells 4 and 5, so (4, 4) is a self-face
+    rc, out, msg = _upload(mutate(m))
+    assert rc == rt.RT_EINVAL and out is None, (name, rc, msg)
+    assert why in msg, (name, msg)
+
+
+@pytest.mark.parametrize("kw,why", [(dict(k_max=0), b"k_max"), (dict(k_max=129), b"k_max"),
+                                    (dict(flags=8), b"flags"), (dict(box=0.0), b"box"),
+                                    (dict(box=float("nan")), b"box")])
+def test_upload_refuses_bad_scalars_on_the_host(kw, why):
+    rc, out, msg = _upload(_lattice(), **kw)
+    assert rc == rt.RT_EINVAL and out is None and why in msg, (kw, msg)
