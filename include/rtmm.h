@@ -129,11 +129,14 @@ int rt_angles_layout(int32_t K, const double *dir, const double *weight, int32_t
  * refuses it with RT_EINVAL unless this call recorded that exact claim (same K,
  * layout, dir and weight pointers).  RT_ANGLES_GENERAL needs no check: the general
  * kernels hold for any set.  The call copies dir [K][3] and weight [K] to the host
- * (synchronising `stream`), classifies them as rt_angles_layout does, and returns
- * RT_EINVAL (recording nothing) when the claim differs from what the arrays hold.
+ * (synchronising `stream`), checks that every direction is a unit vector (within
+ * 1e-10) and that the weights are non-negative and sum to one (within 1e-10), for
+ * every layout, then classifies them as rt_angles_layout does and returns RT_EINVAL
+ * (recording nothing) when the claim differs from what the arrays hold.
  * The arrays must not change while the claim is recorded: call rt_angles_release
  * before changing or freeing them.  Errors: RT_EINVAL (NULL, K outside
- * [1, RT_K_MAX], unknown layout, false claim), RT_EHIP.
+ * [1, RT_K_MAX], unknown layout, a direction that is not a unit vector, a negative or
+ * non-finite weight, weights that do not sum to one, false claim), RT_EHIP.
  */
 int rt_angles_check(const rt_angles *angles, void *stream);
 

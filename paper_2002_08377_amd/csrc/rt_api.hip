@@ -250,12 +250,22 @@ int rt_angles_check(const rt_angles *a, void *stream) {
   if (!a->dir || !a->weight) return fail(RT_EINVAL, "angle arrays are NULL");
   if (a->layout != RT_ANGLES_GENERAL && a->layout != RT_ANGLES_ANTIPODAL && a->layout != RT_ANGLES_ANTIPODAL_ADJACENT)
     return fail(RT_EINVAL, "unknown angle layout %d", a->layout);
-  if (a->layout == RT_ANGLES_GENERAL) return RT_OK;  // the general kernels hold for any set
   hipStream_t st = (hipStream_t)stream;
   std::vector<double> d(3 * (size_t)a->K), w((size_t)a->K);
   RT_HIP(hipMemcpyAsync(d.data(), a->dir, sizeof(double) * d.size(), hipMemcpyDeviceToHost, st), "copy directions");
   RT_HIP(hipMemcpyAsync(w.data(), a->weight, sizeof(double) * w.size(), hipMemcpyDeviceToHost, st), "copy weights");
   RT_HIP(hipStreamSynchronize(st), "angle copy");
+  // the discrete ordinates of section 2.1: unit directions, non-negative weights summing to one
+  double wsum = 0.0;
+  for (int k = 0; k < a->K; ++k) {
+    const double *n = &d[3 * (size_t)k];
+    const double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(fabs(nn - 1.0) < 1e-10)) return fail(RT_EINVAL, "direction %d is not a unit vector", k);
+    if (!(w[k] >= 0.0) || !isfinite(w[k])) return fail(RT_EINVAL, "weight %d is negative or not finite", k);
+    wsum += w[k];
+  }
+  if (!(fabs(wsum - 1.0) <= 1e-10)) return fail(RT_EINVAL, "the weights sum to %.17g, not one", wsum);
+  if (a->layout == RT_ANGLES_GENERAL) return RT_OK;  // the general kernels hold for any such set
   int32_t found = RT_ANGLES_GENERAL;
   int rc = rt_angles_layout(a->K, d.data(), w.data(), &found);
   if (rc) return rc;

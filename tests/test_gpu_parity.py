@@ -939,6 +939,25 @@ def test_error_paths():
     assert e.value.code == rt.RT_ENONFINITE
 
 
+
+def test_angle_check_refuses_sets_that_are_not_discrete_ordinates():
+    """rt_angles_check (which every AngleSet calls) verifies the discrete ordinates of
+    section 2.1 for every layout: unit directions, non-negative weights summing to one."""
+    d, w = inp.angle_set(24)
+    assert rt.AngleSet(d, w).layout == rt.ANGLES_ANTIPODAL
+    bad = []
+    d1 = d.copy(); d1[3] *= 1.001; bad.append((d1, w, b"not a unit vector"))
+    d2 = d.copy(); d2[5, 0] = np.nan; bad.append((d2, w, b"not a unit vector"))
+    w1 = w.copy(); w1[2] = -w1[2]; bad.append((d, w1, b"negative"))
+    w2 = 2.0 * w; bad.append((d, w2, b"sum"))
+    w3 = w.copy(); w3[0] = np.nan; bad.append((d, w3, b"not finite"))
+    for layout in (rt.ANGLES_GENERAL, None):
+        for dd, ww, why in bad:
+            with pytest.raises(rt.RTError) as e:
+                rt.AngleSet(dd, ww, layout=rt.ANGLES_GENERAL if layout is not None else rt.ANGLES_ANTIPODAL)
+            assert e.value.code == rt.RT_EINVAL
+            assert why in rt.lib().rt_last_error(), rt.lib().rt_last_error()
+
 def test_layout_claims_are_verified():
     """An antipodal layout claim reaches the paired kernels only after rt_angles_check has
     verified it against the device arrays: a false claim is refused by the check, an
