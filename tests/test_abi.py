@@ -155,7 +155,9 @@ def test_marked_upload_validates_on_the_host():
 
 def test_angles_check_rejects_bad_claims_on_the_host():
     """rt_angles_check refuses NULL sets, K out of range and unknown layouts before it
-    reads any device memory, and accepts a general claim without reading it."""
+    reads any device memory (the contents of a set, unit directions and normalised weights,
+    are checked on its device copy: a GPU test covers that), and releasing a claim that was
+    never recorded does nothing."""
     L = rt.lib()
     assert L.rt_angles_check(None, None) == rt.RT_EINVAL
     assert L.rt_angles_release(None) == rt.RT_EINVAL
@@ -165,7 +167,6 @@ def test_angles_check_rejects_bad_claims_on_the_host():
         a = rt._Angles(K, layout, d, w)
         assert L.rt_angles_check(ctypes.byref(a), None) == rt.RT_EINVAL, (K, layout)
     a = rt._Angles(8, rt.ANGLES_GENERAL, bogus, bogus)
-    assert L.rt_angles_check(ctypes.byref(a), None) == rt.RT_OK
     assert L.rt_angles_release(ctypes.byref(a)) == rt.RT_OK
 
 
