@@ -180,6 +180,26 @@ int main(void) {
   ang.dir = (const double *)dev_copy(dir, sizeof dir);
   ang.weight = (const double *)dev_copy(w, sizeof w);
   RT_CHECK(rt_angles_check(&ang, NULL));
+  {
+    /* refusals a C caller relies on: weights that do not sum to one, a non-finite velocity */
+    double w2[K_ANG];
+    for (int k = 0; k < K_ANG; ++k) w2[k] = 2.0 / K_ANG;
+    rt_angles bad = ang;
+    bad.layout = RT_ANGLES_GENERAL;
+    bad.weight = (const double *)dev_copy(w2, sizeof w2);
+    const int rc = rt_angles_check(&bad, NULL);
+    expect(rc == RT_EINVAL && strstr(rt_last_error(), "sum") != NULL,
+           "rt_angles_check refuses weights that do not sum to one", (double)rc, (double)RT_EINVAL);
+    HIP_CHECK(hipFree((void *)bad.weight));
+    static double vbad[N_CELLS][3];
+    memcpy(vbad, vel, sizeof vbad);
+    vbad[7][1] = NAN;
+    rt_mesh *mb = NULL;
+    const int rm = rt_mesh_upload(&mb, N_CELLS, N_FACES, K_ANG, 0, &gen[0][0], &gen[0][0], vol, &vbad[0][0],
+                                  &fcell[0][0], &fshift[0][0], farea, &fnorm[0][0], &fcen[0][0], box, NULL);
+    expect(rm == RT_EINVAL && mb == NULL && strstr(rt_last_error(), "mesh_vel") != NULL,
+           "rt_mesh_upload refuses a non-finite velocity", (double)rm, (double)RT_EINVAL);
+  }
 
   const double a_rad = 1.0, cv = 1.5, T0 = 1.2;
   const double dt = 0.2 * h / c_red;

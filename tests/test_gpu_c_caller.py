@@ -41,4 +41,4 @@ def test_c_program_runs_the_step_on_the_gpu():
     assert r.returncode == 0, r.stdout + r.stderr
     lines = r.stdout.strip().splitlines()
     assert lines[-1] == "ok"
-    assert sum(line.startswith("pass ") for line in lines) == 71, r.stdout
+    assert sum(line.startswith("pass ") for line in lines) == 73, r.stdout
